@@ -1,0 +1,201 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics, not by the
+oracle itself: closed-form MNI supports (Section 2.2 definition), counts of
+connected graphs, brute force on tiny graphs, and invariances."""
+import itertools
+import math
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.brute as brute
+import synth
+
+
+def edges_of(pairs):
+    s = np.array([a for a, b in pairs], np.int32)
+    d = np.array([b for a, b in pairs], np.int32)
+    return s, d
+
+
+def by_size(res):
+    out = {}
+    for n, labs, adj, sup in res:
+        out.setdefault(n, []).append((labs, adj, sup))
+    return out
+
+
+def test_star_supports():
+    # K_{1,6}, one label.  The edge pattern's two endpoints form one orbit, so
+    # its domain is every vertex (d+1); any larger star pattern pins its centre
+    # to the single hub, so its support is 1.
+    d = 6
+    s, t = edges_of([(0, i) for i in range(1, d + 1)])
+    lab = np.zeros(d + 1, np.int32)
+    res = by_size(oracle.mine(d + 1, s, t, lab, 1, 5))
+    assert [x[2] for x in res[2]] == [d + 1]
+    for k in (3, 4, 5):
+        assert len(res[k]) == 1 and res[k][0][2] == 1
+    # threshold 2 keeps only the edge
+    assert [r[0] for r in oracle.mine(d + 1, s, t, lab, 2, 5)] == [2]
+
+
+@pytest.mark.parametrize("m", [7, 9, 10])
+def test_path_supports(m):
+    # Path with m vertices: a k-vertex sub-path pattern has orbits {j, k-1-j};
+    # the innermost orbit is smallest: m-k+1 images for odd k, m-k+2 for even.
+    s, t = edges_of([(i, i + 1) for i in range(m - 1)])
+    lab = np.zeros(m, np.int32)
+    res = by_size(oracle.mine(m, s, t, lab, 1, 6))
+    for k in range(2, 7):
+        assert len(res[k]) == 1
+        want = m - k + 1 if k % 2 else m - k + 2
+        assert res[k][0][2] == want
+
+
+def test_cycle_supports():
+    # Cycle C_6: rotations put every vertex in every position, so every path
+    # pattern and the cycle itself have support 6.
+    m = 6
+    s, t = edges_of([(i, (i + 1) % m) for i in range(m)])
+    lab = np.zeros(m, np.int32)
+    res = by_size(oracle.mine(m, s, t, lab, 1, 6))
+    assert [len(res[k]) for k in range(2, 7)] == [1, 1, 1, 1, 2]
+    assert all(x[2] == m for k in res for x in res[k])
+
+
+@pytest.mark.parametrize("m,top", [(6, 6)])
+def test_clique_pattern_counts(m, top):
+    # On K_m every connected graph with k <= m vertices is a pattern with
+    # support m.  The number of connected unlabelled graphs on k = 2..6
+    # vertices is 1, 2, 6, 21, 112 (Section 4.1 quotes six for k = 4).
+    s, t = edges_of(list(itertools.combinations(range(m), 2)))
+    lab = np.zeros(m, np.int32)
+    res = by_size(oracle.mine(m, s, t, lab, 1, top))
+    assert [len(res[k]) for k in range(2, top + 1)] == [1, 2, 6, 21, 112][:top - 1]
+    assert all(x[2] == m for k in res for x in res[k])
+
+
+@pytest.mark.slow
+def test_clique_seven_vertex_patterns():
+    # 853 connected unlabelled graphs on 7 vertices.
+    s, t = edges_of(list(itertools.combinations(range(7), 2)))
+    lab = np.zeros(7, np.int32)
+    res = by_size(oracle.mine(7, s, t, lab, 7, 7))
+    assert len(res[7]) == 853
+
+
+def test_complete_bipartite():
+    # K_{3,5}, sides labelled 0 (3 vertices) and 1 (5 vertices): the edge
+    # pattern has support min(3, 5); no same-label edge exists.
+    a, b = 3, 5
+    s, t = edges_of([(i, a + j) for i in range(a) for j in range(b)])
+    lab = np.array([0] * a + [1] * b, np.int32)
+    res = by_size(oracle.mine(a + b, s, t, lab, 1, 3))
+    assert res[2] == [((0, 1), 1, 3)]
+    # wedges: centre on side 0 (leaves on side 1) and centre on side 1
+    sup3 = sorted(x[2] for x in res[3])
+    assert sup3 == [3, 3]
+
+
+def test_labels_split_patterns():
+    # Triangle with labels (0,0,1): size-2 patterns (0,0) and (0,1).  The
+    # (0,0) edge's endpoints share one orbit; the triangle has support 1 on
+    # the label-1 vertex.
+    s, t = edges_of([(0, 1), (1, 2), (0, 2)])
+    lab = np.array([0, 0, 1], np.int32)
+    res = by_size(oracle.mine(3, s, t, lab, 1, 3))
+    assert [(x[0], x[2]) for x in res[2]] == [((0, 0), 2), ((0, 1), 1)]
+    assert (((0, 0, 1), 7, 1)) in res[3]
+
+
+CONNECTED_LABELLED = [1, 1, 4, 38, 728, 26704]   # connected graphs on k labelled vertices
+
+
+@pytest.mark.parametrize("m", [5, 6, 7])
+def test_count_connected_clique(m):
+    # In K_m every k-vertex set carries c(k) connected spanning edge sets.
+    s, t = edges_of(list(itertools.combinations(range(m), 2)))
+    for k in range(1, min(m, 6) + 1):
+        assert oracle.count_connected(m, s, t, k) == math.comb(m, k) * CONNECTED_LABELLED[k - 1]
+
+
+def test_count_connected_matches_brute():
+    for seed in range(25):
+        s, t, lab = synth.tiny_graph(seed, 8, 11, 2)
+        _, counts = brute.mine(len(lab), s, t, lab, 1, 6, with_counts=True)
+        for k in range(2, 7):
+            assert oracle.count_connected(len(lab), s, t, k) == counts.get(k, 0), (seed, k)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_oracle_matches_brute_force(seed):
+    s, t, lab = synth.tiny_graph(1000 + seed, 8, 11, 1 + seed % 3)
+    n = len(lab)
+    for sup in (1, 2, 3):
+        assert oracle.mine(n, s, t, lab, sup, 5) == brute.mine(n, s, t, lab, sup, 5)
+
+
+def test_oracle_matches_brute_force_size6():
+    for seed in range(6):
+        s, t, lab = synth.tiny_graph(2000 + seed, 7, 10, 2)
+        n = len(lab)
+        assert oracle.mine(n, s, t, lab, 1, 6) == brute.mine(n, s, t, lab, 1, 6)
+
+
+def test_canonical_invariant_under_relabelling():
+    rng = random.Random(7)
+    for _ in range(200):
+        n = rng.randint(2, 7)
+        labs = [rng.randint(0, 2) for _ in range(n)]
+        pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+        adj = 0
+        for k, _p in enumerate(pairs):
+            if rng.random() < 0.4:
+                adj |= 1 << k
+        perm = list(range(n))
+        rng.shuffle(perm)
+        labs2 = [0] * n
+        for i in range(n):
+            labs2[perm[i]] = labs[i]
+        adj2 = 0
+        for k, (i, j) in enumerate(pairs):
+            if adj >> k & 1:
+                a, b = sorted((perm[i], perm[j]))
+                adj2 |= 1 << oracle.pair_index(a, b, n)
+        assert oracle.canonical(labs, adj) == oracle.canonical(labs2, adj2)
+        cl, ca = oracle.canonical(labs, adj)
+        assert list(cl) == sorted(labs)
+
+
+def test_pattern_support_agrees_with_mine():
+    w = synth.workload("er3300")
+    res = oracle.mine(w["n"], w["src"], w["dst"], w["vertex_labels"], 10, 4)
+    rng = random.Random(3)
+    for n, labs, adj, sup in rng.sample(res, 12):
+        assert oracle.pattern_support(w["n"], w["src"], w["dst"], w["vertex_labels"],
+                                      labs, adj) == sup
+
+
+def test_threshold_monotone():
+    # Raising t can only remove patterns and never changes a kept support.
+    w = synth.workload("er3300")
+    args = (w["n"], w["src"], w["dst"], w["vertex_labels"])
+    lo = {(n, l, a): s for n, l, a, s in oracle.mine(*args, 3, 4)}
+    hi = {(n, l, a): s for n, l, a, s in oracle.mine(*args, 10, 4)}
+    assert set(hi) <= set(lo)
+    assert all(lo[k] == v for k, v in hi.items())
+    assert all(v >= 10 for v in hi.values())
+    assert all(v < 10 for k, v in lo.items() if k not in hi)
+
+
+def test_rejects_bad_input():
+    s, t = edges_of([(0, 1)])
+    with pytest.raises(ValueError):
+        oracle.mine(2, s, t, np.array([0, 0], np.int32), 0, 3)
+    with pytest.raises(ValueError):
+        oracle.mine(2, s, t, np.array([0, 0], np.int32), 1, 8)
+    with pytest.raises(ValueError):
+        oracle.mine(2, np.array([0], np.int32), np.array([5], np.int32),
+                    np.array([0, 0], np.int32), 1, 3)
