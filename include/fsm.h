@@ -1,0 +1,225 @@
+/*
+ * fsm.h -- C ABI of the MI355X (gfx950) two-vertex-exploration frequent
+ * subgraph miner.
+ *
+ * Problem (Section 2.2 of Jiang, Wang and Wu, "Efficient Mining of Frequent
+ * Subgraphs with Two-Vertex Exploration"): given an undirected graph whose
+ * vertices carry labels, a threshold t and a maximum size s, find every
+ * connected vertex-labelled pattern P with 2 <= |V_P| <= s whose MNI support
+ *     sigma(P) = min over pattern vertices v of |{ f(v) : f an embedding }|
+ * is at least t.  Embeddings are edge-induced: injective, label-preserving
+ * maps carrying every pattern edge onto a graph edge (Section 6.1 setting).
+ *
+ * Method (Sections 3-4): size-n subgraphs are produced level by level by
+ * joining the size-(n-2) subgraphs of frequent patterns with size-3 subgraphs
+ * (wedges, triangles) on one common vertex (Theorem 1), read from CSR
+ * adjacency restricted to frequent labelled edges; each joined subgraph gets
+ * an index-based quick pattern (Section 4.4), quick patterns are mapped to
+ * canonical patterns, MNI domains are accumulated in per-(pattern, orbit)
+ * bitmaps and patterns below t are filtered before the next join.
+ *
+ * Conventions for every call:
+ *   - Every function returning int returns FSM_OK (0) or a negative
+ *     fsm_status; nothing throws across this boundary.  On failure a
+ *     thread-local message is available from fsm_last_error().
+ *   - Input arrays are HOST pointers, read during the call only; the caller
+ *     keeps ownership.  Handles (fsm_graph, fsm_result) are owned by the
+ *     library and released with the matching *_free call.
+ *   - Device work runs on the stream set by fsm_set_stream (default: the
+ *     null stream) and allocates through the hooks set by fsm_set_allocator
+ *     (default: hipMalloc / hipFree).  Each call synchronises its stream
+ *     before returning.
+ */
+#ifndef FSM_H
+#define FSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Largest pattern size supported (vertices). */
+#define FSM_MAX_SIZE 7
+/* Largest number of distinct labels that can be frequent in one call. */
+#define FSM_MAX_FREQ_LABELS 64
+
+typedef struct fsm_graph fsm_graph;    /* device-resident CSR, immutable */
+typedef struct fsm_result fsm_result;  /* host-resident mining result */
+
+/* Canonical code of a pattern (36 bytes, little-endian).
+ *   n        number of vertices (2..7)
+ *   label[i] label of canonical vertex i (the caller's label values), -1
+ *            for i >= n; labels are non-decreasing in i
+ *   adj      bit k set when the k-th vertex pair (i<j), counted in row-major
+ *            upper-triangle order (0,1),(0,2),...,(0,n-1),(1,2),..., is an
+ *            edge
+ * The canonical form is the vertex order whose (label sequence, pair bit
+ * sequence (0,1),(0,2),...) is lexicographically smallest over all n! orders
+ * (one fixed choice of the canonical form that Section 2.1 leaves to a
+ * tool); two patterns are isomorphic iff their codes are equal.  Results are
+ * ordered by (n, label sequence, pair bit sequence). */
+typedef struct {
+    int32_t n;
+    int32_t label[FSM_MAX_SIZE];
+    uint32_t adj;
+} fsm_code;
+
+/* Mode bits for fsm_mine / fsm_options.mode. */
+enum {
+    FSM_PLAIN = 0,    /* level-by-level exact join (Sections 3-4) */
+    FSM_BATCHED = 1,  /* reserved: persistent multi-graph scheduling */
+    FSM_LEARNED = 2,  /* reserved: learned cost model for sizing */
+    FSM_SAMPLED = 4   /* subgraph sampling during joining (Section 5) */
+};
+
+typedef enum {
+    FSM_OK = 0,
+    FSM_EINVAL = -1,       /* invalid argument; nothing was done */
+    FSM_ENOMEM = -2,       /* device or host allocation failed */
+    FSM_EDEVICE = -3,      /* a HIP runtime call or kernel failed */
+    FSM_EOVERFLOW = -4,    /* a size limit was exceeded (see message) */
+    FSM_EUNSUPPORTED = -5  /* valid request outside this build's limits */
+} fsm_status;
+
+/* Per-level counters of one mining call (index = pattern size). */
+typedef struct {
+    int64_t parents;      /* size-(n-2) embeddings joined (n >= 4) */
+    int64_t work_items;   /* (parent, joining position) pairs */
+    int64_t candidates;   /* (work item, size-3 piece) slots enumerated */
+    int64_t emitted;      /* subgraphs produced (valid, dissection-accepted,
+                             not pruned); for sizes 2 and 3 the edges and
+                             size-3 subgraphs over frequent labelled edges */
+    int64_t quick_patterns;   /* distinct quick patterns */
+    int64_t patterns;         /* distinct canonical patterns seen */
+    int64_t frequent;         /* patterns with support >= t */
+    int64_t stored;           /* embeddings kept for the next join */
+    int64_t algorithmic_bytes;  /* bytes the join's domain pass must move:
+                                   parent rows, the neighbour lists it
+                                   enumerates, 8 per adjacency probe, 4 per
+                                   domain-bitmap word of each emitted
+                                   subgraph position */
+    double kernel_ms;         /* device time of this level (all passes) */
+    double join_ms;           /* device time of the join's domain pass */
+} fsm_level_stats;
+
+typedef struct {
+    int32_t max_size;
+    int32_t frequent_labels;
+    int64_t dropped_self_loops;    /* from fsm_build_graph */
+    int64_t dropped_duplicates;    /* duplicate undirected edges merged */
+    int64_t filtered_edges;        /* undirected edges whose labelled edge is frequent */
+    fsm_level_stats level[FSM_MAX_SIZE + 1];
+    double total_ms;               /* wall time of the mining call */
+} fsm_stats;
+
+/* Options of fsm_mine_ex.  Zero-initialise, then set fields. */
+typedef struct {
+    int64_t support;          /* MNI threshold t >= 1 */
+    int32_t max_size;         /* 2..7 */
+    uint32_t mode;            /* FSM_PLAIN or FSM_SAMPLED */
+    int32_t disable_pruning;  /* 1: skip the Section 4.5 pruning (results
+                                 are identical; counters differ) */
+    int32_t reserved0;
+    double sampling_rate;     /* FSM_SAMPLED: keep probability of a size-3
+                                 piece per key group, in (0, 1] */
+    uint64_t seed;            /* FSM_SAMPLED: hash seed */
+    int64_t hash_capacity_min;  /* >0: initial quick-pattern table slots
+                                   (grown on overflow) */
+    int64_t pool_bytes_min;     /* >0: initial domain-bitmap pool bytes
+                                   (grown on overflow) */
+} fsm_options;
+
+/* Allocation hooks used for all device memory of later calls (e.g. a
+ * framework's caching allocator).  Both NULL restores hipMalloc/hipFree.
+ * alloc(bytes, ctx) returns device memory or NULL; release(ptr, ctx). */
+int fsm_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                      void (*release)(void *ptr, void *ctx), void *ctx);
+
+/* Stream (a hipStream_t, NULL = null stream) used by later calls. */
+int fsm_set_stream(void *hip_stream);
+
+/* Build the device CSR of a labelled undirected graph (the input graph
+ * G = (V, E, L) of Section 2.1, vertex labels only).
+ *   n_vertices      number of vertices, ids 0..n_vertices-1 (>= 1)
+ *   n_edges         length of src/dst (>= 0)
+ *   src, dst        host int32 arrays: one undirected edge per index, in any
+ *                   order and direction; self-loops are dropped and repeated
+ *                   pairs merged (counts in fsm_result_stats)
+ *   vertex_labels   host int32 array of n_vertices labels, each in
+ *                   [0, 2^24)
+ *   out             receives the handle (NULL on failure)
+ * Errors: FSM_EINVAL for NULL pointers, n_vertices < 1, an id out of range
+ * or a label out of range; FSM_EUNSUPPORTED when the CSR would exceed 2^31-1
+ * directed entries; FSM_ENOMEM / FSM_EDEVICE from the device. */
+int fsm_build_graph(int64_t n_vertices, int64_t n_edges, const int32_t *src,
+                    const int32_t *dst, const int32_t *vertex_labels,
+                    fsm_graph **out);
+
+/* Number of vertices / undirected edges of a built graph (-1 for NULL). */
+int64_t fsm_graph_vertices(const fsm_graph *g);
+int64_t fsm_graph_edges(const fsm_graph *g);
+
+/* Mine every frequent pattern of sizes 2..max_size (Section 2.2 problem,
+ * Section 3 workflow: size-3 matching, support filtering, two-vertex joins,
+ * aggregation).
+ *   support    MNI threshold t (>= 1); a pattern is kept iff sigma >= t
+ *   max_size   2..7
+ *   mode       FSM_PLAIN (FSM_SAMPLED needs fsm_mine_ex)
+ *   out        receives the result handle
+ * Errors: FSM_EINVAL (NULL graph/out, support < 1, max_size outside 2..7,
+ * unknown mode bits, FSM_SAMPLED here); FSM_EUNSUPPORTED when more than
+ * FSM_MAX_FREQ_LABELS labels occur on at least `support` vertices;
+ * FSM_EOVERFLOW when a table cannot grow within device memory;
+ * FSM_ENOMEM / FSM_EDEVICE from the device. */
+int fsm_mine(const fsm_graph *g, int64_t support, int32_t max_size,
+             uint32_t mode, fsm_result **out);
+
+/* fsm_mine with options.  FSM_SAMPLED keeps each size-3 piece of a key group
+ * at every join with probability sampling_rate, decided by a counter-based
+ * hash of (seed, level, joining vertex, the piece's vertices) -- subgraph
+ * sampling during joining (Section 5); supports are then MNI over the
+ * sampled embeddings (a lower bound).  Errors as fsm_mine, plus FSM_EINVAL
+ * for a sampling rate outside (0, 1]. */
+int fsm_mine_ex(const fsm_graph *g, const fsm_options *opt, fsm_result **out);
+
+/* Number of frequent patterns in a result (-1 for NULL). */
+int64_t fsm_result_count(const fsm_result *r);
+
+/* Copy the patterns out, ordered by (size, canonical code).  Each array
+ * argument may be NULL (skipped) or must hold fsm_result_count(r) entries.
+ *   ids       0..count-1, the rank in that order
+ *   sizes     pattern sizes
+ *   codes     canonical codes
+ *   supports  exact MNI supports (sampled mode: supports over the sample) */
+int fsm_result_patterns(const fsm_result *r, int32_t *ids, int32_t *sizes,
+                        fsm_code *codes, int64_t *supports);
+
+/* Per-level counters and timings of the call that produced r. */
+int fsm_result_stats(const fsm_result *r, fsm_stats *s);
+
+void fsm_graph_free(fsm_graph *g);
+void fsm_result_free(fsm_result *r);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *fsm_last_error(void);
+
+/* Smallest-vertex-first dissection (Section 4.3, Algorithm 1), run on the
+ * host with the same code the device join uses.  For a connected graph on
+ * n (4..7) vertices with distinct ids, it picks the one split of the vertex
+ * set into a connected 3-vertex part l and a connected (n-2)-vertex part r
+ * sharing one vertex v' that the join accepts: l is the lexicographically
+ * smallest sorted id triple for which such a v' exists, v' the smallest one.
+ *   n        vertices; ids[i] their ids (distinct)
+ *   adj      LSB-first pair bits as in fsm_code (row-major upper triangle)
+ *   l_mask   receives the positions of l (bit i = vertex i)
+ *   shared   receives the position of v'
+ * Returns FSM_OK, FSM_EINVAL for bad arguments or a disconnected graph. */
+int fsm_dissect(int32_t n, const int32_t *ids, uint32_t adj, uint32_t *l_mask,
+                int32_t *shared);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSM_H */

@@ -1,0 +1,279 @@
+"""Python binding of the MI355X two-vertex-exploration frequent subgraph
+miner (``include/fsm.h``).
+
+Argument marshalling only: every step of mining runs in ``libfsm.so``.  The
+library must have been built (``paper_2101_07690_amd.build.build()``);
+importing this package without it raises, there is no fallback.
+
+Results are lists of ``(size, labels, adj, support)`` ordered by size, then
+canonical label sequence, then canonical pair-bit sequence; ``labels`` is a
+tuple of the caller's label values of the canonical vertices and ``adj`` has
+bit ``k`` set when the k-th vertex pair (i<j), in row-major upper-triangle
+order, is an edge.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsm.so")
+
+FSM_PLAIN = 0
+FSM_BATCHED = 1
+FSM_LEARNED = 2
+FSM_SAMPLED = 4
+MAX_SIZE = 7
+
+STATUS = {0: "FSM_OK", -1: "FSM_EINVAL", -2: "FSM_ENOMEM", -3: "FSM_EDEVICE",
+          -4: "FSM_EOVERFLOW", -5: "FSM_EUNSUPPORTED"}
+
+
+class FsmError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{STATUS.get(code, code)}: {message}")
+        self.code = code
+
+
+class Code(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("label", ctypes.c_int32 * MAX_SIZE),
+                ("adj", ctypes.c_uint32)]
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("parents", ctypes.c_int64), ("work_items", ctypes.c_int64),
+                ("candidates", ctypes.c_int64), ("emitted", ctypes.c_int64),
+                ("quick_patterns", ctypes.c_int64), ("patterns", ctypes.c_int64),
+                ("frequent", ctypes.c_int64), ("stored", ctypes.c_int64),
+                ("algorithmic_bytes", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("max_size", ctypes.c_int32), ("frequent_labels", ctypes.c_int32),
+                ("dropped_self_loops", ctypes.c_int64),
+                ("dropped_duplicates", ctypes.c_int64),
+                ("filtered_edges", ctypes.c_int64),
+                ("level", LevelStats * (MAX_SIZE + 1)),
+                ("total_ms", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("support", ctypes.c_int64), ("max_size", ctypes.c_int32),
+                ("mode", ctypes.c_uint32), ("disable_pruning", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
+                ("pool_bytes_min", ctypes.c_int64)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "paper_2101_07690_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.fsm_set_allocator.argtypes = [_ALLOC_FN, _RELEASE_FN, vp]
+    L.fsm_set_allocator.restype = ctypes.c_int
+    L.fsm_set_stream.argtypes = [vp]
+    L.fsm_set_stream.restype = ctypes.c_int
+    L.fsm_build_graph.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i32p,
+                                  ctypes.POINTER(vp)]
+    L.fsm_build_graph.restype = ctypes.c_int
+    L.fsm_graph_vertices.argtypes = [vp]
+    L.fsm_graph_vertices.restype = ctypes.c_int64
+    L.fsm_graph_edges.argtypes = [vp]
+    L.fsm_graph_edges.restype = ctypes.c_int64
+    L.fsm_mine.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                           ctypes.POINTER(vp)]
+    L.fsm_mine.restype = ctypes.c_int
+    L.fsm_mine_ex.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.fsm_mine_ex.restype = ctypes.c_int
+    L.fsm_result_count.argtypes = [vp]
+    L.fsm_result_count.restype = ctypes.c_int64
+    L.fsm_result_patterns.argtypes = [vp, i32p, i32p, ctypes.POINTER(Code), i64p]
+    L.fsm_result_patterns.restype = ctypes.c_int
+    L.fsm_result_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.fsm_result_stats.restype = ctypes.c_int
+    L.fsm_graph_free.argtypes = [vp]
+    L.fsm_graph_free.restype = None
+    L.fsm_result_free.argtypes = [vp]
+    L.fsm_result_free.restype = None
+    L.fsm_last_error.argtypes = []
+    L.fsm_last_error.restype = ctypes.c_char_p
+    L.fsm_dissect.argtypes = [ctypes.c_int32, i32p, ctypes.c_uint32,
+                              ctypes.POINTER(ctypes.c_uint32), i32p]
+    L.fsm_dissect.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().fsm_last_error()
+        raise FsmError(rc, msg.decode() if msg else "")
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+_torch_hooks = None
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through PyTorch's caching
+    allocator (on the current device and stream), or back to hipMalloc."""
+    global _torch_hooks
+    L = lib()
+    if not enable:
+        _check(L.fsm_set_allocator(_ALLOC_FN(), _RELEASE_FN(), None))
+        _torch_hooks = None
+        return
+    import torch
+
+    def _alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:   # out of memory -> NULL, reported as FSM_ENOMEM
+            return None
+
+    def _release(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
+    _check(L.fsm_set_allocator(hooks[0], hooks[1], None))
+    _torch_hooks = hooks
+
+
+def set_stream(stream=None):
+    """Use a torch.cuda.Stream (or a raw hipStream_t int; None = null stream)."""
+    if stream is None:
+        ptr = None
+    elif isinstance(stream, int):
+        ptr = stream
+    else:
+        ptr = stream.cuda_stream
+    _check(lib().fsm_set_stream(ptr))
+
+
+class Graph:
+    """Device-resident CSR of a labelled undirected graph (fsm_build_graph)."""
+
+    def __init__(self, n_vertices, src, dst, labels):
+        L = lib()
+        s, sp = _i32(src)
+        d, dp = _i32(dst)
+        lab, lp = _i32(labels)
+        if s.shape != d.shape:
+            raise ValueError("src and dst differ in length")
+        if lab.size != n_vertices:
+            raise ValueError("labels must have n_vertices entries")
+        h = ctypes.c_void_p()
+        _check(L.fsm_build_graph(int(n_vertices), int(s.size), sp, dp, lp, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_vertices(self):
+        return int(lib().fsm_graph_vertices(self._h))
+
+    @property
+    def n_edges(self):
+        return int(lib().fsm_graph_edges(self._h))
+
+    def close(self):
+        if self._h:
+            lib().fsm_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Result:
+    """Host copy of one mining result: ``patterns`` and ``stats``."""
+
+    def __init__(self, handle):
+        L = lib()
+        try:
+            cnt = L.fsm_result_count(handle)
+            sizes = np.zeros(max(cnt, 1), np.int32)
+            sup = np.zeros(max(cnt, 1), np.int64)
+            codes = (Code * max(cnt, 1))()
+            _check(L.fsm_result_patterns(
+                handle, None, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), codes,
+                sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+            st = Stats()
+            _check(L.fsm_result_stats(handle, ctypes.byref(st)))
+        finally:
+            L.fsm_result_free(handle)
+        self.patterns = [(int(codes[i].n), tuple(int(codes[i].label[j]) for j in range(codes[i].n)),
+                          int(codes[i].adj), int(sup[i])) for i in range(cnt)]
+        self.stats = _stats_dict(st)
+
+
+def _stats_dict(st):
+    levels = {}
+    for n in range(2, st.max_size + 1):
+        lv = st.level[n]
+        levels[n] = {f: getattr(lv, f) for f, _ in LevelStats._fields_}
+    return {"max_size": st.max_size, "frequent_labels": st.frequent_labels,
+            "dropped_self_loops": st.dropped_self_loops,
+            "dropped_duplicates": st.dropped_duplicates,
+            "filtered_edges": st.filtered_edges, "levels": levels,
+            "total_ms": st.total_ms}
+
+
+def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
+         sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
+         hash_capacity_min: int = 0, pool_bytes_min: int = 0) -> Result:
+    """Frequent patterns of sizes 2..max_size with MNI support >= support."""
+    o = Options()
+    o.support = int(support)
+    o.max_size = int(max_size)
+    o.mode = int(mode)
+    o.disable_pruning = 1 if disable_pruning else 0
+    o.sampling_rate = float(sampling_rate)
+    o.seed = int(seed) & ((1 << 64) - 1)
+    o.hash_capacity_min = int(hash_capacity_min)
+    o.pool_bytes_min = int(pool_bytes_min)
+    h = ctypes.c_void_p()
+    _check(lib().fsm_mine_ex(graph.handle, ctypes.byref(o), ctypes.byref(h)))
+    return Result(h)
+
+
+def dissect(ids, adj):
+    """Host instance of the join's dissection rule: (l_mask, shared position)."""
+    n = len(ids)
+    a, ap = _i32(ids)
+    lm = ctypes.c_uint32()
+    sh = ctypes.c_int32()
+    _check(lib().fsm_dissect(n, ap, ctypes.c_uint32(adj), ctypes.byref(lm), ctypes.byref(sh)))
+    return int(lm.value), int(sh.value)

@@ -1,0 +1,235 @@
+// abi.cpp -- the extern "C" boundary: argument validation, error codes and
+// messages, allocation / stream hooks, handle lifetime.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+#include "internal.h"
+
+namespace fsm {
+namespace {
+
+thread_local char g_err[512] = "";
+
+struct Hooks {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+    hipStream_t stream = nullptr;
+};
+Hooks g_hooks;
+
+void hip_release(void* p, void*) { (void)hipFree(p); }
+
+template <class F>
+int guarded(F&& f) {
+    g_err[0] = '\0';
+    try {
+        f();
+        return FSM_OK;
+    } catch (const Failure& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return FSM_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FSM_EDEVICE;
+    }
+}
+
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    throw Failure{code};
+}
+
+hipStream_t stream() { return g_hooks.stream; }
+
+void* raw_alloc(size_t bytes, void** ctx, void (**release)(void*, void*)) {
+    void* p = nullptr;
+    if (g_hooks.alloc) {
+        p = g_hooks.alloc(bytes, g_hooks.ctx);
+        if (!p) fail(FSM_ENOMEM, "device allocation of %zu bytes failed", bytes);
+        *ctx = g_hooks.ctx;
+        *release = g_hooks.release;
+        return p;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? FSM_ENOMEM : FSM_EDEVICE,
+             "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    *ctx = nullptr;
+    *release = hip_release;
+    return p;
+}
+
+}  // namespace fsm
+
+using namespace fsm;
+
+extern "C" {
+
+int fsm_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+    g_err[0] = '\0';
+    if ((alloc == nullptr) != (release == nullptr)) {
+        set_error("fsm_set_allocator: give both hooks or neither");
+        return FSM_EINVAL;
+    }
+    g_hooks.alloc = alloc;
+    g_hooks.release = release;
+    g_hooks.ctx = alloc ? ctx : nullptr;
+    return FSM_OK;
+}
+
+int fsm_set_stream(void* hip_stream) {
+    g_err[0] = '\0';
+    g_hooks.stream = static_cast<hipStream_t>(hip_stream);
+    return FSM_OK;
+}
+
+int fsm_build_graph(int64_t n_vertices, int64_t n_edges, const int32_t* src, const int32_t* dst,
+                    const int32_t* vertex_labels, fsm_graph** out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out) fail(FSM_EINVAL, "fsm_build_graph: out is NULL");
+        if (n_vertices < 1 || n_vertices > INT32_MAX)
+            fail(FSM_EINVAL, "fsm_build_graph: n_vertices must be in [1, 2^31-1]");
+        if (n_edges < 0) fail(FSM_EINVAL, "fsm_build_graph: n_edges < 0");
+        if (!vertex_labels) fail(FSM_EINVAL, "fsm_build_graph: vertex_labels is NULL");
+        if (n_edges > 0 && (!src || !dst)) fail(FSM_EINVAL, "fsm_build_graph: src/dst is NULL");
+        for (int64_t e = 0; e < n_edges; ++e)
+            if (src[e] < 0 || src[e] >= n_vertices || dst[e] < 0 || dst[e] >= n_vertices)
+                fail(FSM_EINVAL, "fsm_build_graph: edge %lld has an endpoint out of range",
+                     (long long)e);
+        for (int64_t v = 0; v < n_vertices; ++v)
+            if (vertex_labels[v] < 0 || vertex_labels[v] >= (1 << 24))
+                fail(FSM_EINVAL, "fsm_build_graph: label of vertex %lld outside [0, 2^24)",
+                     (long long)v);
+        if (n_edges > (int64_t)INT32_MAX)
+            fail(FSM_EUNSUPPORTED, "fsm_build_graph: more than 2^31-1 edges");
+        fsm_graph* g = new fsm_graph();
+        try {
+            FSM_HIP(hipGetDevice(&g->device));
+            build_graph(g, n_vertices, n_edges, src, dst, vertex_labels);
+        } catch (...) {
+            delete g;
+            throw;
+        }
+        *out = g;
+    });
+}
+
+int64_t fsm_graph_vertices(const fsm_graph* g) { return g ? g->n : -1; }
+int64_t fsm_graph_edges(const fsm_graph* g) { return g ? g->nnz / 2 : -1; }
+
+int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!g || !opt || !out) fail(FSM_EINVAL, "fsm_mine: NULL argument");
+        if (opt->support < 1) fail(FSM_EINVAL, "fsm_mine: support must be >= 1");
+        if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
+            fail(FSM_EINVAL, "fsm_mine: max_size must be in [2, %d]", FSM_MAX_SIZE);
+        if (opt->mode & ~(uint32_t)FSM_SAMPLED)
+            fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
+        if ((opt->mode & FSM_SAMPLED) &&
+            !(opt->sampling_rate > 0.0 && opt->sampling_rate <= 1.0))
+            fail(FSM_EINVAL, "fsm_mine: sampling_rate must be in (0, 1]");
+        fsm_result* r = new fsm_result();
+        try {
+            mine(g, *opt, r);
+        } catch (...) {
+            delete r;
+            throw;
+        }
+        *out = r;
+    });
+}
+
+int fsm_mine(const fsm_graph* g, int64_t support, int32_t max_size, uint32_t mode,
+             fsm_result** out) {
+    if (mode & FSM_SAMPLED) {
+        if (out) *out = nullptr;
+        set_error("fsm_mine: FSM_SAMPLED needs fsm_mine_ex (rate and seed)");
+        return FSM_EINVAL;
+    }
+    fsm_options o;
+    memset(&o, 0, sizeof(o));
+    o.support = support;
+    o.max_size = max_size;
+    o.mode = mode;
+    o.sampling_rate = 1.0;
+    return fsm_mine_ex(g, &o, out);
+}
+
+int64_t fsm_result_count(const fsm_result* r) { return r ? (int64_t)r->size.size() : -1; }
+
+int fsm_result_patterns(const fsm_result* r, int32_t* ids, int32_t* sizes, fsm_code* codes,
+                        int64_t* supports) {
+    return guarded([&] {
+        if (!r) fail(FSM_EINVAL, "fsm_result_patterns: NULL result");
+        for (size_t i = 0; i < r->size.size(); ++i) {
+            if (ids) ids[i] = (int32_t)i;
+            if (sizes) sizes[i] = r->size[i];
+            if (codes) codes[i] = r->code[i];
+            if (supports) supports[i] = r->support[i];
+        }
+    });
+}
+
+int fsm_result_stats(const fsm_result* r, fsm_stats* s) {
+    return guarded([&] {
+        if (!r || !s) fail(FSM_EINVAL, "fsm_result_stats: NULL argument");
+        *s = r->stats;
+    });
+}
+
+void fsm_graph_free(fsm_graph* g) { delete g; }
+void fsm_result_free(fsm_result* r) { delete r; }
+
+const char* fsm_last_error(void) { return g_err; }
+
+int fsm_dissect(int32_t n, const int32_t* ids, uint32_t adj, uint32_t* l_mask, int32_t* shared) {
+    return guarded([&] {
+        if (n < 4 || n > FSM_MAX_SIZE || !ids || !l_mask || !shared)
+            fail(FSM_EINVAL, "fsm_dissect: bad arguments");
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if (ids[i] == ids[j]) fail(FSM_EINVAL, "fsm_dissect: ids must be distinct");
+        uint64_t A = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if ((adj >> pair_pos(i, j, n)) & 1u) A = add_edge(A, i, j);
+        if (!connected((1u << n) - 1u, A, n)) fail(FSM_EINVAL, "fsm_dissect: graph not connected");
+        uint64_t ob = 0;
+        for (int p = 0; p < n; ++p) {
+            int r = 0;
+            for (int q = 0; q < n; ++q) r += ids[q] < ids[p] ? 1 : 0;
+            ob |= (uint64_t)(1u << p) << (8 * r);
+        }
+        uint32_t vb = 0;
+        uint32_t l = dissect(n, ob, A, &vb);
+        if (!l) fail(FSM_EINVAL, "fsm_dissect: no dissection");
+        *l_mask = l;
+        int sh = 0;
+        while (!((vb >> sh) & 1u)) ++sh;
+        *shared = sh;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// internal.h -- host-side plumbing shared by the library's sources: device
+// buffers through the caller's allocation hooks, the current stream, error
+// reporting, and the graph / result objects behind the C ABI handles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fsm.h"
+
+namespace fsm {
+
+// Internal failure carrying an fsm_status; caught at the ABI boundary.
+struct Failure {
+    int code;
+};
+
+void set_error(const char* fmt, ...);
+[[noreturn]] void fail(int code, const char* fmt, ...);
+
+#define FSM_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            ::fsm::fail(e_ == hipErrorOutOfMemory ? FSM_ENOMEM : FSM_EDEVICE,      \
+                        "%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,  \
+                        __LINE__);                                                 \
+    } while (0)
+
+#define FSM_LAUNCH_CHECK() FSM_HIP(hipGetLastError())
+
+hipStream_t stream();
+
+void* raw_alloc(size_t bytes, void** release_ctx, void (**release)(void*, void*));
+
+// Device allocation owned by one object; freed with the hook that made it.
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void (*rel)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept { swap(o); }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) { reset(); swap(o); }
+        return *this;
+    }
+    ~DBuf() { reset(); }
+
+    void swap(DBuf& o) noexcept {
+        std::swap(p, o.p); std::swap(n, o.n); std::swap(rel, o.rel); std::swap(ctx, o.ctx);
+    }
+    void alloc(size_t count) {
+        reset();
+        if (count == 0) count = 1;
+        p = static_cast<T*>(raw_alloc(count * sizeof(T), &ctx, &rel));
+        n = count;
+    }
+    void reset() {
+        if (p && rel) rel(p, ctx);
+        p = nullptr; n = 0; rel = nullptr; ctx = nullptr;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    void zero() {
+        if (p) FSM_HIP(hipMemsetAsync(p, 0, bytes(), stream()));
+    }
+    void fill_bytes(int v) {
+        if (p) FSM_HIP(hipMemsetAsync(p, v, bytes(), stream()));
+    }
+};
+
+template <class T>
+void to_host(std::vector<T>& h, const T* d, size_t count) {
+    h.resize(count);
+    if (count) FSM_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, stream()));
+    FSM_HIP(hipStreamSynchronize(stream()));
+}
+
+template <class T>
+T scalar_to_host(const T* d) {
+    T v;
+    FSM_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, stream()));
+    FSM_HIP(hipStreamSynchronize(stream()));
+    return v;
+}
+
+template <class T>
+void to_device(T* d, const T* h, size_t count) {
+    if (count) FSM_HIP(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, stream()));
+}
+
+// Exclusive prefix sum of n int64 values (in == out allowed); returns the total.
+int64_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n);
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace fsm
+
+// Objects behind the opaque ABI handles.
+struct fsm_graph {
+    int device = 0;
+    int64_t n = 0;             // vertices
+    int64_t nnz = 0;           // directed CSR entries (2 x undirected edges)
+    int32_t num_labels = 0;    // distinct labels
+    fsm::DBuf<int32_t> row;    // n+1
+    fsm::DBuf<int32_t> col;    // nnz, ascending within each row
+    fsm::DBuf<int32_t> lab;    // n, dense label rank 0..num_labels-1
+    std::vector<int32_t> label_value;   // rank -> caller's label
+    std::vector<int64_t> label_count;   // vertices per rank
+    int64_t dropped_loops = 0;
+    int64_t dropped_dups = 0;
+};
+
+struct fsm_result {
+    std::vector<int32_t> size;
+    std::vector<fsm_code> code;
+    std::vector<int64_t> support;
+    fsm_stats stats{};
+};
+
+namespace fsm {
+void build_graph(fsm_graph* g, int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                 const int32_t* labels);
+void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r);
+}  // namespace fsm

@@ -1,0 +1,1265 @@
+// mine.hip -- the level-by-level two-vertex-exploration miner.
+//
+// Levels (Section 3 workflow):
+//   size 2  labelled edges over frequent labels            (Step 2)
+//   size 3  wedges and triangles over frequent edges       (Steps 1-2)
+//   size n  join of size-(n-2) embeddings of frequent patterns with size-3
+//           pieces on one common vertex (Section 4.1, Theorem 1), over CSR
+//           adjacency restricted to frequent labelled edges  (Step 3)
+// Every produced subgraph gets a quick pattern (QP, Section 4.4); a QP table
+// maps it to a canonical pattern and to the automorphism orbit of each of its
+// positions; MNI domains (Section 2.2) are bitmaps per (pattern, orbit);
+// patterns below t are dropped and, when a later join needs them, the
+// embeddings of frequent patterns are compacted by count / scan / fill
+// (Step 4).
+//
+// Recording a subgraph (any level):
+//   QP key  -> open-addressing table slot s (insert by CAS)
+//   value[s] = VALID | FREQ | bitmap region << 21 | 3-bit orbit slot per
+//              position; absent on first sight, then the lane computes the
+//              canonical form itself (deterministic), finds / inserts the
+//              code in the pattern table, allocates the pattern's bitmaps
+//              from a pool on first use (CAS), and publishes the value
+//   bits    -> for each position p: set bit v_p in bitmap (region, slot_p),
+//              reading first and issuing the atomicOr only when unset
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "internal.h"
+
+namespace fsm {
+namespace {
+
+constexpr int TPB = 256;
+constexpr uint64_t VALID = 1ull << 63;
+constexpr uint64_t FREQ = 1ull << 62;
+constexpr uint64_t REGION_MASK = (1ull << 41) - 1;
+constexpr int JOIN_CHUNK = 4;   // work items fetched per queue access
+
+enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, OVF_POOL = 4, ERR_MISSING = 8, ERR_FILL = 16 };
+enum { MODE_DOMAIN = 0, MODE_COUNT = 1, MODE_FILL = 2 };
+enum { PIECE_KC = 0, PIECE_KL = 1, PIECE_TR = 2 };   // k-centre wedge, k-leaf wedge, triangle
+
+struct QPTab {
+    uint64_t* kv;      // 2 words per slot: key, value
+    uint64_t mask;     // capacity - 1
+    uint64_t* adj;     // packed adjacency of the QP's ordered subgraph
+    int32_t* pat;      // pattern-table slot
+    unsigned* count;   // occupied slots
+};
+
+struct CodeTab {
+    uint64_t* kv;      // 2 words per slot: canonical code, bitmap region + 1
+    uint64_t mask;
+    uint64_t* info;    // VALID | 3-bit orbit representative per canonical position
+    int64_t* sup;      // MNI support after the reduction
+    unsigned* count;
+};
+
+struct Pool {
+    uint32_t* words;
+    uint64_t nwords;
+    unsigned long long* ctr;   // words handed out
+    uint32_t W;                // words per bitmap
+};
+
+struct Rec {
+    QPTab q;
+    CodeTab c;
+    Pool pool;
+    uint32_t* flags;
+    int n;             // subgraph size of this level
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_excl(int64_t v, int lane) {
+    int64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    return inc - v;
+}
+
+// Find `key`; insert it when `insert` (CAS on an empty slot).  Returns the
+// slot, or -1 when absent (lookup) or the table is full (flag raised).
+__device__ int64_t ht_probe(uint64_t* kv, uint64_t mask, uint64_t key, bool insert,
+                            unsigned* count, uint32_t* flags, uint32_t bit) {
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t i = 0; i <= mask; ++i) {
+        uint64_t cur = kv[2 * h];
+        if (cur == key) return (int64_t)h;
+        if (cur == EMPTY_KEY) {
+            if (!insert) return -1;
+            unsigned long long prev =
+                atomicCAS((unsigned long long*)&kv[2 * h], (unsigned long long)EMPTY_KEY,
+                          (unsigned long long)key);
+            if (prev == EMPTY_KEY) {
+                unsigned c = atomicAdd(count, 1u);
+                if ((uint64_t)c * 2 > mask) atomicOr(flags, bit);   // keep load <= 1/2
+                return (int64_t)h;
+            }
+            if (prev == key) return (int64_t)h;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicOr(flags, bit);
+    return -1;
+}
+
+__device__ __forceinline__ uint64_t load_value(uint64_t* p) {
+    uint64_t v = *p;
+    if (!(v & VALID)) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return v;
+}
+
+// First sight of QP slot s: canonical form, pattern slot, bitmap region.
+__device__ __noinline__ uint64_t publish_qp(const Rec& R, int64_t s, uint64_t L, uint64_t A) {
+    Canon cn = canonicalize(R.n, L, A);
+    int64_t p = ht_probe(R.c.kv, R.c.mask, cn.code, true, R.c.count, R.flags, OVF_CODE);
+    if (p < 0) return 0;
+    uint64_t* regp = &R.c.kv[2 * p + 1];
+    uint64_t reg = __hip_atomic_load(regp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (reg == 0) {
+        const unsigned long long need = (unsigned long long)R.n * R.pool.W;
+        unsigned long long base = atomicAdd(R.pool.ctr, need);
+        if (base + need > R.pool.nwords) {
+            atomicOr(R.flags, OVF_POOL);
+            return 0;
+        }
+        unsigned long long mine = base / R.pool.W + 1;
+        unsigned long long prev = atomicCAS((unsigned long long*)regp, 0ull, mine);
+        reg = prev == 0 ? mine : prev;
+    }
+    R.c.info[p] = VALID | cn.orbits;
+    R.q.adj[s] = A;
+    R.q.pat[s] = (int32_t)p;
+    uint64_t val = VALID | ((reg - 1) << 21) | cn.slots;
+    __hip_atomic_store(&R.q.kv[2 * s + 1], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return val;
+}
+
+__device__ __forceinline__ void set_bit(uint32_t* w, int32_t v) {
+    uint32_t bit = 1u << (v & 31);
+    if (!(*w & bit)) atomicOr(w, bit);
+}
+
+template <int N>
+__device__ __forceinline__ void record_bits(const Rec& R, uint64_t val, const int32_t (&v)[N]) {
+    const uint64_t region = (val >> 21) & REGION_MASK;
+    uint32_t* base = R.pool.words + region * R.pool.W;
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
+        set_bit(base + (uint64_t)slot * R.pool.W + (uint32_t)(v[p] >> 5), v[p]);
+    }
+}
+
+// Domain pass: record one subgraph; returns its QP slot (or -1).
+template <int N>
+__device__ __forceinline__ int64_t record(const Rec& R, uint64_t key, uint64_t L, uint64_t A,
+                                          const int32_t (&v)[N]) {
+    int64_t s = ht_probe(R.q.kv, R.q.mask, key, true, R.q.count, R.flags, OVF_QP);
+    if (s < 0) return -1;
+    uint64_t val = load_value(&R.q.kv[2 * s + 1]);
+    if (!(val & VALID)) {
+        val = publish_qp(R, s, L, A);
+        if (!val) return -1;
+    }
+    record_bits<N>(R, val, v);
+    return s;
+}
+
+// Count / fill passes: QP slot of a subgraph of a frequent pattern, else -1.
+__device__ __forceinline__ int64_t frequent_slot(const Rec& R, uint64_t key) {
+    int64_t s = ht_probe(R.q.kv, R.q.mask, key, false, nullptr, R.flags, ERR_MISSING);
+    if (s < 0) {
+        atomicOr(R.flags, ERR_MISSING);
+        return -1;
+    }
+    return (R.q.kv[2 * s + 1] & FREQ) ? s : -1;
+}
+
+__device__ __forceinline__ bool has_edge(const uint64_t* eset, uint64_t emask, int32_t a,
+                                         int32_t b) {
+    uint64_t key = a < b ? ((uint64_t)(uint32_t)a << 32 | (uint32_t)b)
+                         : ((uint64_t)(uint32_t)b << 32 | (uint32_t)a);
+    uint64_t h = mix64(key) & emask;
+    for (;;) {   // load <= 1/4, so an empty slot ends every probe
+        uint64_t k = eset[h];
+        if (k == key) return true;
+        if (k == EMPTY_KEY) return false;
+        h = (h + 1) & emask;
+    }
+}
+
+__device__ __forceinline__ int wave_id_global() {
+    return (int)(blockIdx.x * (TPB / 64) + (threadIdx.x >> 6));
+}
+
+// ------------------------------------------------------------- setup kernels
+
+__global__ void k_init_table(uint64_t* kv, uint64_t slots) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        kv[2 * s] = EMPTY_KEY;
+        kv[2 * s + 1] = 0;
+    }
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_vertex_flabel(const int32_t* lab, int64_t n, const int32_t* fmap, int32_t* vf) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        vf[v] = fmap[lab[v]];
+}
+
+// frequent-edge subgraph G_f: keep (v, w) when both labels are frequent and
+// the labelled edge is frequent
+__global__ void k_gf_count(const int32_t* row, const int32_t* col, const int32_t* vf, int64_t n,
+                           const uint8_t* freq2, int F, int64_t* cnt) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        int a = vf[v];
+        if (a >= 0)
+            for (int32_t e = row[v]; e < row[v + 1]; ++e) {
+                int b = vf[col[e]];
+                if (b >= 0 && freq2[a * F + b]) ++c;
+            }
+        cnt[v] = c;
+    }
+}
+
+__global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t* vf, int64_t n,
+                          const uint8_t* freq2, int F, const int64_t* off, int64_t total,
+                          int32_t* frow, int32_t* fcol) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (v == n) { frow[n] = (int32_t)total; continue; }
+        int64_t o = off[v];
+        frow[v] = (int32_t)o;
+        int a = vf[v];
+        if (a < 0) continue;
+        for (int32_t e = row[v]; e < row[v + 1]; ++e) {
+            int32_t w = col[e];
+            int b = vf[w];
+            if (b >= 0 && freq2[a * F + b]) fcol[o++] = w;
+        }
+    }
+}
+
+__global__ void k_eset_insert(const int32_t* row, const int32_t* col, int64_t n, uint64_t* eset,
+                              uint64_t emask) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        for (int32_t e = row[u]; e < row[u + 1]; ++e) {
+            int32_t w = col[e];
+            if (w <= u) continue;
+            uint64_t key = (uint64_t)(uint32_t)u << 32 | (uint32_t)w;
+            uint64_t h = mix64(key) & emask;
+            for (;;) {
+                unsigned long long prev = atomicCAS((unsigned long long*)&eset[h],
+                                                    (unsigned long long)EMPTY_KEY,
+                                                    (unsigned long long)key);
+                if (prev == EMPTY_KEY || prev == key) break;
+                h = (h + 1) & emask;
+            }
+        }
+    }
+}
+
+// pieces rooted at k: centre pairs C(d,2) plus one slot per (u in N(k),
+// w in N(u)) for k-leaf wedges; leafoff = per-row prefix of neighbour degrees
+__global__ void k_pieces(const int32_t* row, const int32_t* col, int64_t n, int64_t* npieces,
+                         int32_t* leafoff) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = row[k + 1] - row[k];
+        int64_t s = 0;
+        for (int32_t e = row[k]; e < row[k + 1]; ++e) {
+            leafoff[e] = (int32_t)s;
+            int32_t u = col[e];
+            s += row[u + 1] - row[u];
+        }
+        npieces[k] = d * (d - 1) / 2 + s;
+    }
+}
+
+// --------------------------------------------------------------- level 2
+
+struct L2Args {
+    const int32_t* row;
+    const int32_t* col;
+    const int32_t* vf;
+    int64_t n;
+    Rec R;
+    unsigned long long* emitted;
+    int64_t* counts;
+    const int64_t* offsets;
+    int32_t* out;
+    int64_t out_rows;
+};
+
+// One wave per vertex u; lanes over neighbours w > u with a frequent label.
+// Stored order (u, w), u < w; QP = the ordered label pair.
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_level2(L2Args a) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (TPB / 64);
+    unsigned long long emit = 0;
+    for (int64_t u = wave_id_global(); u < a.n; u += nwaves) {
+        const int lu = a.vf[u];
+        if (lu < 0) continue;
+        const int32_t rb = a.row[u], re = a.row[u + 1];
+        int64_t base = (MODE == MODE_FILL) ? a.offsets[u] : 0, total = 0;
+        for (int32_t e0 = rb; e0 < re; e0 += 64) {
+            const int32_t e = e0 + lane;
+            int32_t w = -1;
+            int lw = -1;
+            if (e < re) {
+                w = a.col[e];
+                lw = w > u ? a.vf[w] : -1;
+            }
+            int64_t s = -1;
+            if (lw >= 0) {
+                uint64_t key = (uint64_t)lu << 6 | (uint64_t)lw;
+                if (MODE == MODE_DOMAIN) {
+                    int32_t v[2] = {(int32_t)u, w};
+                    uint64_t L = (uint64_t)lu | (uint64_t)lw << 6;
+                    record<2>(a.R, key, L, add_edge(0, 0, 1), v);
+                    ++emit;
+                } else {
+                    s = frequent_slot(a.R, key);
+                }
+            }
+            if (MODE != MODE_DOMAIN) {
+                int64_t c = s >= 0 ? 1 : 0;
+                int64_t ex = wave_excl(c, lane);
+                if (MODE == MODE_FILL && c) {
+                    int64_t r = base + total + ex;
+                    if (r < a.out_rows) {
+                        int32_t* o = a.out + r * 3;
+                        o[0] = (int32_t)u; o[1] = w; o[2] = (int32_t)s;
+                    } else {
+                        atomicOr(a.R.flags, ERR_FILL);
+                    }
+                }
+                total += wave_sum(c);
+            }
+        }
+        if (MODE == MODE_COUNT && lane == 0) a.counts[u] = total;
+    }
+    if (MODE == MODE_DOMAIN) {
+        int64_t t = wave_sum((int64_t)emit);
+        if (lane == 0 && t) atomicAdd(a.emitted, (unsigned long long)t);
+    }
+}
+
+// --------------------------------------------------------------- level 3
+
+struct L3Args {
+    const int32_t* row;    // G_f
+    const int32_t* col;
+    const int32_t* vf;
+    int64_t n;
+    const uint64_t* eset;
+    uint64_t emask;
+    Rec R;
+    unsigned long long* emitted;
+    int64_t* counts;
+    const int64_t* offsets;
+    int32_t* out;
+    int64_t out_rows;
+};
+
+__device__ __forceinline__ void decode_pair(int64_t r, int32_t* a, int32_t* b) {
+    // pairs (a<b) listed by b, then a: index = b(b-1)/2 + a
+    int64_t bb = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)r)) * 0.5f);
+    while (bb * (bb - 1) / 2 > r) --bb;
+    while ((bb + 1) * bb / 2 <= r) ++bb;
+    *b = (int32_t)bb;
+    *a = (int32_t)(r - bb * (bb - 1) / 2);
+}
+
+// One wave per centre c; lanes over neighbour pairs u < w.  Each pair is a
+// wedge (c; u, w) stored (c, u, w); when c < u and u ~ w it is also the
+// triangle stored (c, u, w) (each triangle once, at its smallest vertex).
+// QP = (type, labels in stored order).
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (TPB / 64);
+    unsigned long long emit = 0;
+    for (int64_t c = wave_id_global(); c < a.n; c += nwaves) {
+        const int32_t rb = a.row[c];
+        const int64_t d = a.row[c + 1] - rb;
+        const int64_t npairs = d * (d - 1) / 2;
+        if (npairs == 0) {
+            if (MODE == MODE_COUNT && lane == 0) a.counts[c] = 0;
+            continue;
+        }
+        const int lc = a.vf[c];
+        int64_t base = (MODE == MODE_FILL) ? a.offsets[c] : 0, total = 0;
+        for (int64_t r0 = 0; r0 < npairs; r0 += 64) {
+            const int64_t r = r0 + lane;
+            int32_t u = -1, w = -1;
+            bool tri = false;
+            int lu = 0, lw = 0;
+            if (r < npairs) {
+                int32_t ia, ib;
+                decode_pair(r, &ia, &ib);
+                u = a.col[rb + ia];
+                w = a.col[rb + ib];
+                lu = a.vf[u];
+                lw = a.vf[w];
+                tri = c < u && has_edge(a.eset, a.emask, u, w);
+            }
+            const uint64_t L = (uint64_t)lc | (uint64_t)lu << 6 | (uint64_t)lw << 12;
+            const uint64_t kw = (uint64_t)lc << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
+            const uint64_t kt = (1ull << 18) | kw;
+            const uint64_t Aw = add_edge(add_edge(0, 0, 1), 0, 2);
+            const int32_t v[3] = {(int32_t)c, u, w};
+            if (MODE == MODE_DOMAIN) {
+                if (u >= 0) {
+                    record<3>(a.R, kw, L, Aw, v);
+                    ++emit;
+                    if (tri) {
+                        record<3>(a.R, kt, L, add_edge(Aw, 1, 2), v);
+                        ++emit;
+                    }
+                }
+            } else {
+                int64_t sw = -1, stt = -1;
+                if (u >= 0) {
+                    sw = frequent_slot(a.R, kw);
+                    if (tri) stt = frequent_slot(a.R, kt);
+                }
+                int64_t cnum = (sw >= 0 ? 1 : 0) + (stt >= 0 ? 1 : 0);
+                int64_t ex = wave_excl(cnum, lane);
+                if (MODE == MODE_FILL && cnum) {
+                    int64_t r2 = base + total + ex;
+                    if (r2 + cnum <= a.out_rows) {
+                        int32_t* o = a.out + r2 * 4;
+                        if (sw >= 0) {
+                            o[0] = (int32_t)c; o[1] = u; o[2] = w; o[3] = (int32_t)sw;
+                            o += 4;
+                        }
+                        if (stt >= 0) {
+                            o[0] = (int32_t)c; o[1] = u; o[2] = w; o[3] = (int32_t)stt;
+                        }
+                    } else {
+                        atomicOr(a.R.flags, ERR_FILL);
+                    }
+                }
+                total += wave_sum(cnum);
+            }
+        }
+        if (MODE == MODE_COUNT && lane == 0) a.counts[c] = total;
+    }
+    if (MODE == MODE_DOMAIN) {
+        int64_t t = wave_sum((int64_t)emit);
+        if (lane == 0 && t) atomicAdd(a.emitted, (unsigned long long)t);
+    }
+}
+
+// ----------------------------------------------------------------- join
+
+struct JoinArgs {
+    const int32_t* row;      // G_f
+    const int32_t* col;
+    const int32_t* vf;
+    const int64_t* npieces;
+    const int32_t* leafoff;
+    const uint64_t* eset;
+    uint64_t emask;
+    const uint8_t* f3;       // [2][F][F][F]: 0 wedge (centre first), 1 triangle
+    int F;
+    const int32_t* par;      // parents, rows of (M vertices, QP slot)
+    const uint64_t* padj;    // parent level: packed adjacency per QP slot
+    Rec R;
+    unsigned long long* work_ctr;
+    int64_t nwork;
+    unsigned long long* emitted;
+    unsigned long long* cands;
+    unsigned long long* bytes;
+    int prune;
+    int sampled;
+    uint64_t seed;
+    uint64_t sample_thr;     // keep a piece when its hash is below this
+    int64_t* counts;
+    const int64_t* offsets;
+    int32_t* out;
+    int64_t out_rows;
+};
+
+__device__ __forceinline__ bool f3_at(const uint8_t* f3, int F, int t, int a, int b, int c) {
+    return f3[((t * F + a) * F + b) * F + c] != 0;
+}
+
+// Counter-based keep decision of a size-3 piece with vertex set {k, u, w}
+// joined at level n (subgraph sampling during joining, Section 5).
+__device__ __forceinline__ uint64_t sample_hash(uint64_t seed, int n, int32_t k, int32_t u,
+                                                int32_t w) {
+    uint64_t lo = (uint32_t)(u < w ? u : w), hi = (uint32_t)(u < w ? w : u);
+    uint64_t h = mix64(seed ^ ((uint64_t)n << 56));
+    h = mix64(h ^ (uint64_t)(uint32_t)k);
+    h = mix64(h ^ (lo << 32 | hi));
+    return h;
+}
+
+// All children of one (parent, position, piece-vertex pair) candidate.
+// PHASE 0: domain pass (record) or count pass (count); PHASE 1: fill pass,
+// writing rows from `dst`.  Returns the number of children accepted.
+template <int N, int MODE, int PHASE>
+__device__ int children(const JoinArgs& a, const int32_t (&cv)[N], int i, uint32_t types,
+                       uint32_t ec, uint64_t PA, uint64_t L, uint64_t ob, int32_t pslot, int lu,
+                       int lw, int32_t* dst) {
+    constexpr int M = N - 2;
+    const uint32_t Tstar = (1u << i) | (1u << M) | (1u << (M + 1));
+    const uint32_t kbit = 1u << i;
+    int got = 0;
+    const int lk = lab_at(L, i);
+    for (int t = 0; t < 3; ++t) {
+        if (!((types >> t) & 1u)) continue;
+        uint64_t A0 = add_edge(PA, i, M);
+        if (t == PIECE_KC) A0 = add_edge(A0, i, M + 1);
+        else if (t == PIECE_KL) A0 = add_edge(A0, M, M + 1);
+        else A0 = add_edge(add_edge(A0, i, M + 1), M, M + 1);
+        const uint64_t kbase = (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)t << 30 |
+                               (uint64_t)lu << 24 | (uint64_t)lw << 18;
+        uint32_t sub = ec;
+        for (;;) {
+            uint64_t A = A0;
+            uint32_t cb = 0;
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if ((sub >> (2 * j)) & 1u) { A = add_edge(A, j, M); cb |= 1u << (3 * j + 1); }
+                if ((sub >> (2 * j + 1)) & 1u) { A = add_edge(A, j, M + 1); cb |= 1u << (3 * j + 2); }
+            }
+            if (a.prune && sub) {
+                // Section 4.5: a size-3 subgraph around the joining vertex k
+                // spanning both sides must be a frequent size-3 pattern
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        if (!((sub >> (2 * j + q)) & 1u) || !ok) continue;
+                        const int c = M + q;
+                        const bool kb = (amask(A, i) >> j) & 1u;
+                        const bool kc = (amask(A, i) >> c) & 1u;
+                        const int lb = lab_at(L, j), lc = lab_at(L, c);
+                        if (kb && kc) ok = f3_at(a.f3, a.F, 1, lk, lb, lc);
+                        else if (kb) ok = f3_at(a.f3, a.F, 0, lb, lk, lc);
+                        else if (kc) ok = f3_at(a.f3, a.F, 0, lc, lk, lb);
+                    }
+                }
+            }
+            if (ok && dissection_is(N, ob, A, Tstar, kbit)) {
+                const uint64_t key = kbase | cb;
+                if (MODE == MODE_DOMAIN) {
+                    record<N>(a.R, key, L, A, cv);
+                    ++got;
+                } else {
+                    int64_t s = frequent_slot(a.R, key);
+                    if (s >= 0) {
+                        if (PHASE == 1) {
+#pragma unroll
+                            for (int p = 0; p < N; ++p) dst[p] = cv[p];
+                            dst[N] = (int32_t)s;
+                            dst += N + 1;
+                        }
+                        ++got;
+                    }
+                }
+            }
+            if (!sub) break;
+            sub = (sub - 1) & ec;
+        }
+    }
+    return got;
+}
+
+// Two-vertex join (Section 4.1-4.3).  Work item = (parent p, position i),
+// k = p[i]; one wave per work item (fetched from a queue in chunks), lanes
+// over the pieces rooted at k: centre pairs (u, w) of N(k) (k-centre wedge,
+// plus the triangle when u ~ w) and leaf slots (u in N(k), w in N(u)).
+template <int N, int MODE>
+__global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
+    constexpr int M = N - 2;
+    const int lane = threadIdx.x & 63;
+    unsigned long long emit = 0, cands = 0, bytes = 0;
+    for (;;) {
+        unsigned long long w0 = 0;
+        if (lane == 0) w0 = atomicAdd(a.work_ctr, (unsigned long long)JOIN_CHUNK);
+        w0 = __shfl(w0, 0, 64);
+        if ((int64_t)w0 >= a.nwork) break;
+        const int64_t wend = min((int64_t)w0 + JOIN_CHUNK, a.nwork);
+        for (int64_t wi = (int64_t)w0; wi < wend; ++wi) {
+            const int64_t p = wi / M;
+            const int i = (int)(wi - p * M);
+            const int32_t* prow = a.par + p * (M + 1);
+            int32_t cv[N];
+#pragma unroll
+            for (int j = 0; j < M; ++j) cv[j] = prow[j];
+            const int32_t pslot = prow[M];
+            const uint64_t PA = a.padj[pslot];
+            int32_t k = cv[0], mu = INT_MAX;
+            uint64_t L = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j == i) k = cv[j];
+                else mu = min(mu, cv[j]);
+                L |= (uint64_t)a.vf[cv[j]] << (6 * j);
+            }
+            const int lk = a.vf[k];
+            const int32_t rk = a.row[k];
+            const int32_t dk = a.row[k + 1] - rk;
+            const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
+            const int64_t Pk = a.npieces[k];
+            if (lane == 0) {
+                cands += (unsigned long long)Pk;
+                // parent row, N(k), and the N(u) rows of the k-leaf slots
+                bytes += 4ull * (M + 1) + 4ull * (unsigned long long)(dk + (Pk - ncen));
+            }
+            int64_t base = (MODE == MODE_FILL) ? a.offsets[wi] : 0, total = 0;
+            for (int64_t r0 = 0; r0 < Pk; r0 += 64) {
+                const int64_t r = r0 + lane;
+                int32_t u = -1, w = -1;
+                uint32_t types = 0;
+                if (r < Pk) {
+                    bool centre = r < ncen;
+                    if (centre) {
+                        int32_t ia, ib;
+                        decode_pair(r, &ia, &ib);
+                        u = a.col[rk + ia];
+                        w = a.col[rk + ib];
+                    } else {
+                        const int32_t rr = (int32_t)(r - ncen);
+                        int32_t lo = 0, hi = dk - 1;   // last ia with leafoff[rk+ia] <= rr
+                        while (lo < hi) {
+                            int32_t mid = (lo + hi + 1) >> 1;
+                            if (a.leafoff[rk + mid] <= rr) lo = mid; else hi = mid - 1;
+                        }
+                        u = a.col[rk + lo];
+                        w = a.col[a.row[u] + (rr - a.leafoff[rk + lo])];
+                    }
+                    bool ok = w != k;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
+                    // n <= 5: the smallest vertex of every child lies in the
+                    // accepted size-3 part (checked exhaustively for all
+                    // connected graphs on 4 and 5 vertices), so a piece whose
+                    // three vertices all exceed min(parent \ k) is rejected
+                    if (N <= 5 && ok && min(k, min(u, w)) > mu) ok = false;
+                    if (ok && a.sampled &&
+                        sample_hash(a.seed, N, k, u, w) >= a.sample_thr)
+                        ok = false;
+                    if (ok) {
+                        const int lu = a.vf[u], lw = a.vf[w];
+                        if (centre) {
+                            if (f3_at(a.f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
+                            if (f3_at(a.f3, a.F, 1, lk, lu, lw)) {
+                                bytes += 8;
+                                if (has_edge(a.eset, a.emask, u, w)) types |= 1u << PIECE_TR;
+                            }
+                        } else {
+                            if (f3_at(a.f3, a.F, 0, lu, lk, lw)) types |= 1u << PIECE_KL;
+                        }
+                    }
+                }
+                int64_t got = 0;
+                uint32_t ec = 0;
+                uint64_t Lc = 0, ob = 0;
+                int lu = 0, lw = 0;
+                if (types) {
+                    lu = a.vf[u];
+                    lw = a.vf[w];
+                    cv[M] = u;
+                    cv[M + 1] = w;
+                    Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1));
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        if (j == i) continue;
+                        if (has_edge(a.eset, a.emask, cv[j], u)) ec |= 1u << (2 * j);
+                        if (has_edge(a.eset, a.emask, cv[j], w)) ec |= 1u << (2 * j + 1);
+                    }
+                    ob = rank_bits<N>(cv);
+                    got = children<N, MODE, 0>(a, cv, i, types, ec, PA, Lc, ob, pslot, lu, lw,
+                                               nullptr);
+                    bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
+                }
+                if (MODE == MODE_DOMAIN) {
+                    emit += (unsigned long long)got;
+                } else {
+                    const int64_t ex = wave_excl(got, lane);
+                    if (MODE == MODE_FILL && got) {
+                        // same enumeration again, now writing at this lane's rows
+                        const int64_t r2 = base + total + ex;
+                        if (r2 + got <= a.out_rows)
+                            children<N, MODE, 1>(a, cv, i, types, ec, PA, Lc, ob, pslot, lu, lw,
+                                                 a.out + r2 * (N + 1));
+                        else
+                            atomicOr(a.R.flags, ERR_FILL);
+                    }
+                    total += wave_sum(got);
+                }
+            }
+            if (MODE == MODE_COUNT && lane == 0) a.counts[wi] = total;
+        }
+    }
+    int64_t t = wave_sum((int64_t)emit);
+    int64_t cc = wave_sum((int64_t)cands);
+    int64_t bb = wave_sum((int64_t)bytes);
+    if (lane == 0) {
+        if (t) atomicAdd(a.emitted, (unsigned long long)t);
+        if (cc) atomicAdd(a.cands, (unsigned long long)cc);
+        if (bb) atomicAdd(a.bytes, (unsigned long long)bb);
+    }
+}
+
+// --------------------------------------------------------- MNI reduction
+
+struct MniArgs {
+    CodeTab c;
+    Pool pool;
+    int n;
+    uint64_t slots;
+    uint64_t* out_key;
+    int64_t* out_sup;
+    unsigned* out_n;
+    unsigned out_cap;
+};
+
+// One block per pattern slot: popcount of each orbit bitmap, minimum over
+// orbits (MNI support, Section 2.2).
+__global__ __launch_bounds__(TPB) void k_mni(MniArgs a) {
+    __shared__ unsigned long long part[TPB / 64];
+    for (uint64_t s = blockIdx.x; s < a.slots; s += gridDim.x) {
+        const uint64_t key = a.c.kv[2 * s];
+        if (key == EMPTY_KEY) continue;
+        const uint64_t reg = a.c.kv[2 * s + 1];
+        const uint64_t info = a.c.info[s];
+        int64_t best = -1;
+        if (reg != 0 && (info & VALID)) {
+            const uint32_t* base = a.pool.words + (reg - 1) * a.pool.W;
+            for (int cp = 0; cp < a.n; ++cp) {
+                if ((int)((info >> (3 * cp)) & 7u) != cp) continue;
+                const uint32_t* bm = base + (uint64_t)cp * a.pool.W;
+                unsigned long long cnt = 0;
+                for (uint32_t i = threadIdx.x; i < a.pool.W; i += TPB) cnt += __popc(bm[i]);
+                cnt = (unsigned long long)wave_sum((int64_t)cnt);
+                if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+                __syncthreads();
+                unsigned long long tot = 0;
+                for (int q = 0; q < TPB / 64; ++q) tot += part[q];
+                __syncthreads();
+                if (best < 0 || (int64_t)tot < best) best = (int64_t)tot;
+            }
+        }
+        if (threadIdx.x == 0) {
+            if (best < 0) best = 0;
+            a.c.sup[s] = best;
+            unsigned idx = atomicAdd(a.out_n, 1u);
+            if (idx < a.out_cap) {
+                a.out_key[idx] = key;
+                a.out_sup[idx] = best;
+            }
+        }
+    }
+}
+
+// FREQ bit on every QP whose pattern reached the threshold
+__global__ void k_mark_frequent(QPTab q, uint64_t slots, const int64_t* sup, int64_t t) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        if (q.kv[2 * s] == EMPTY_KEY) continue;
+        uint64_t v = q.kv[2 * s + 1];
+        if ((v & VALID) && sup[q.pat[s]] >= t) q.kv[2 * s + 1] = v | FREQ;
+    }
+}
+
+// ================================================================== host
+
+struct Tables {
+    DBuf<uint64_t> qkv, qadj, ckv, cinfo;
+    DBuf<int32_t> qpat;
+    DBuf<int64_t> csup;
+    DBuf<unsigned> qcount, ccount;
+    uint64_t qcap = 0, ccap = 0;
+
+    void alloc(uint64_t qc, uint64_t cc) {
+        qcap = qc;
+        ccap = cc;
+        qkv.alloc(2 * qc);
+        qadj.alloc(qc);
+        qpat.alloc(qc);
+        ckv.alloc(2 * cc);
+        cinfo.alloc(cc);
+        csup.alloc(cc);
+        qcount.alloc(1);
+        ccount.alloc(1);
+    }
+    void reset() {
+        hipStream_t st = stream();
+        k_init_table<<<grid_for((int64_t)qcap, TPB), TPB, 0, st>>>(qkv.p, qcap);
+        FSM_LAUNCH_CHECK();
+        k_init_table<<<grid_for((int64_t)ccap, TPB), TPB, 0, st>>>(ckv.p, ccap);
+        FSM_LAUNCH_CHECK();
+        qadj.zero();
+        qpat.zero();
+        cinfo.zero();
+        csup.zero();
+        qcount.zero();
+        ccount.zero();
+    }
+};
+
+struct Level {
+    int n = 0;
+    Tables tab;
+    DBuf<int32_t> emb;       // rows of (n vertices, QP slot), frequent patterns only
+    int64_t rows = 0;
+    std::vector<std::pair<uint64_t, int64_t>> freq;   // (code, support), support >= t
+    fsm_level_stats st{};
+};
+
+uint64_t pow2_at_least(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Miner {
+    const fsm_graph* g;
+    fsm_options opt;
+    hipStream_t st;
+    int F = 0;
+    std::vector<int32_t> fvalue;          // frequent id -> caller label
+    DBuf<int32_t> vf;                     // frequent id per vertex or -1
+    DBuf<int32_t> frow, fcol;             // G_f
+    int64_t fnnz = 0;
+    DBuf<uint64_t> eset;
+    uint64_t emask = 0;
+    DBuf<int64_t> npieces;
+    DBuf<int32_t> leafoff;
+    DBuf<uint8_t> f3;
+    DBuf<uint32_t> pool;
+    uint64_t pool_words = 0;
+    DBuf<unsigned long long> pool_ctr, counters;   // [emitted, candidates, work queue, bytes]
+    DBuf<uint32_t> flags;
+    uint32_t W = 1;
+    unsigned grid_persistent = 1024;
+    Level lv[FSM_MAX_SIZE + 1];
+    fsm_result* res;
+
+    uint64_t qcap0() const {
+        uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 16);
+        return pow2_at_least(c);
+    }
+
+    Rec rec(Level& L) {
+        Rec R;
+        R.q = {L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qpat.p, L.tab.qcount.p};
+        R.c = {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
+        R.pool = {pool.p, pool_words, pool_ctr.p, W};
+        R.flags = flags.p;
+        R.n = L.n;
+        return R;
+    }
+
+    void ensure_pool(uint64_t words) {
+        if (words <= pool_words) return;
+        pool.alloc(words);
+        pool_words = words;
+    }
+
+    // Run a domain pass with retries on table / pool overflow, then the MNI
+    // reduction; fills L.freq and the FREQ bits.
+    template <class Launch>
+    void domain_level(Level& L, Launch&& launch) {
+        uint64_t qcap = L.tab.qcap ? L.tab.qcap : qcap0();
+        uint64_t ccap = L.tab.ccap ? L.tab.ccap : (1ull << 12);
+        for (int attempt = 0;; ++attempt) {
+            // child keys carry the parent's QP slot in 29 bits
+            if (qcap > (1ull << 29))
+                fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
+            if (L.tab.qcap != qcap || L.tab.ccap != ccap) L.tab.alloc(qcap, ccap);
+            L.tab.reset();
+            pool.zero();
+            pool_ctr.zero();
+            counters.zero();
+            flags.zero();
+            launch(rec(L));
+            uint32_t f = scalar_to_host(flags.p);
+            if (f & (ERR_MISSING | ERR_FILL))
+                fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", L.n, f);
+            if (!(f & (OVF_QP | OVF_CODE | OVF_POOL))) break;
+            if (attempt >= 8)
+                fail(FSM_EOVERFLOW, "tables kept overflowing at size %d (flags %u)", L.n, f);
+            if (f & OVF_QP) qcap *= 16;
+            if (f & OVF_CODE) ccap *= 16;
+            if (f & OVF_POOL) ensure_pool(pool_words * 8);
+        }
+        std::vector<unsigned long long> cnt;
+        to_host(cnt, counters.p, 4);
+        L.st.emitted = (int64_t)cnt[0];
+        L.st.candidates = (int64_t)cnt[1];
+        L.st.algorithmic_bytes = (int64_t)cnt[3];
+        const unsigned npat = scalar_to_host(L.tab.ccount.p);
+        L.st.quick_patterns = (int64_t)scalar_to_host(L.tab.qcount.p);
+        L.st.patterns = npat;
+        DBuf<uint64_t> okey(npat ? npat : 1);
+        DBuf<int64_t> osup(npat ? npat : 1);
+        DBuf<unsigned> on(1);
+        on.zero();
+        MniArgs m{{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p},
+                  {pool.p, pool_words, pool_ctr.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p,
+                  npat};
+        k_mni<<<grid_for((int64_t)L.tab.ccap, 1, 1u << 16), TPB, 0, st>>>(m);
+        FSM_LAUNCH_CHECK();
+        QPTab q{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qpat.p, L.tab.qcount.p};
+        k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(q, L.tab.qcap,
+                                                                             L.tab.csup.p,
+                                                                             opt.support);
+        FSM_LAUNCH_CHECK();
+        std::vector<uint64_t> hk;
+        std::vector<int64_t> hs;
+        to_host(hk, okey.p, npat);
+        to_host(hs, osup.p, npat);
+        L.freq.clear();
+        for (unsigned i = 0; i < npat; ++i)
+            if (hs[i] >= opt.support) L.freq.emplace_back(hk[i], hs[i]);
+        std::sort(L.freq.begin(), L.freq.end());
+        L.st.frequent = (int64_t)L.freq.size();
+    }
+
+    // count / scan / fill of the frequent embeddings of level L
+    template <class Launch>
+    void materialize(Level& L, int64_t nwork, Launch&& launch) {
+        DBuf<int64_t> counts((size_t)(nwork > 0 ? nwork : 1));
+        counts.zero();
+        flags.zero();
+        counters.zero();
+        launch(MODE_COUNT, counts.p, (const int64_t*)nullptr, (int32_t*)nullptr, (int64_t)0);
+        int64_t total = scan_exclusive(counts.p, counts.p, nwork);
+        L.rows = total;
+        L.emb.alloc((size_t)(total * (L.n + 1) + 1));
+        counters.zero();
+        if (total > 0) launch(MODE_FILL, (int64_t*)nullptr, (const int64_t*)counts.p, L.emb.p, total);
+        uint32_t f = scalar_to_host(flags.p);
+        if (f) fail(FSM_EDEVICE, "materialisation of size %d failed (flags %u)", L.n, f);
+        L.st.stored = total;
+    }
+
+    void run();
+    void level2();
+    void build_gf();
+    void level3();
+    void join(int n);
+    void emit_results();
+};
+
+void Miner::level2() {
+    Level& L = lv[2];
+    L.n = 2;
+    auto launch = [&](Rec R) {
+        L2Args a{g->row.p, g->col.p, vf.p, g->n, R, counters.p, nullptr, nullptr, nullptr, 0};
+        k_level2<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
+        FSM_LAUNCH_CHECK();
+    };
+    domain_level(L, launch);
+}
+
+void Miner::build_gf() {
+    // frequent labelled edges from the size-2 results
+    std::vector<uint8_t> f2((size_t)F * F, 0);
+    for (auto& kv : lv[2].freq) {
+        int a = (int)((kv.first >> (21 + 6)) & 63), b = (int)((kv.first >> 21) & 63);
+        f2[(size_t)a * F + b] = f2[(size_t)b * F + a] = 1;
+    }
+    DBuf<uint8_t> df2(f2.size());
+    to_device(df2.p, f2.data(), f2.size());
+    const int64_t n = g->n;
+    DBuf<int64_t> cnt((size_t)n + 1);
+    k_gf_count<<<grid_for(n, TPB), TPB, 0, st>>>(g->row.p, g->col.p, vf.p, n, df2.p, F, cnt.p);
+    FSM_LAUNCH_CHECK();
+    fnnz = scan_exclusive(cnt.p, cnt.p, n);
+    frow.alloc((size_t)n + 1);
+    fcol.alloc((size_t)(fnnz > 0 ? fnnz : 1));
+    k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row.p, g->col.p, vf.p, n, df2.p, F, cnt.p,
+                                                     fnnz, frow.p, fcol.p);
+    FSM_LAUNCH_CHECK();
+    // edge set (load <= 1/4) and per-vertex piece counts
+    uint64_t ecap = pow2_at_least((uint64_t)(fnnz / 2) * 4 + 16);
+    eset.alloc(ecap);
+    emask = ecap - 1;
+    k_fill_u64<<<grid_for((int64_t)ecap, TPB), TPB, 0, st>>>(eset.p, ecap, EMPTY_KEY);
+    FSM_LAUNCH_CHECK();
+    k_eset_insert<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, eset.p, emask);
+    FSM_LAUNCH_CHECK();
+    npieces.alloc((size_t)n);
+    leafoff.alloc((size_t)(fnnz > 0 ? fnnz : 1));
+    k_pieces<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, npieces.p, leafoff.p);
+    FSM_LAUNCH_CHECK();
+    res->stats.filtered_edges = fnnz / 2;
+}
+
+void Miner::level3() {
+    Level& L = lv[3];
+    L.n = 3;
+    auto launch = [&](Rec R) {
+        L3Args a{frow.p, fcol.p, vf.p, g->n, eset.p, emask, R, counters.p,
+                 nullptr, nullptr, nullptr, 0};
+        k_level3<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
+        FSM_LAUNCH_CHECK();
+    };
+    domain_level(L, launch);
+    // rooted frequent size-3 table for the joins and the pruning
+    const size_t FF = (size_t)F * F * F;
+    std::vector<uint8_t> t(2 * FF, 0);
+    for (auto& kv : L.freq) {
+        const uint64_t code = kv.first;
+        int l0 = (int)((code >> (21 + 12)) & 63), l1 = (int)((code >> (21 + 6)) & 63),
+            l2 = (int)((code >> 21) & 63);
+        const uint32_t seq = (uint32_t)(code & 7u);   // bits: (0,1) (0,2) (1,2)
+        int ls[3] = {l0, l1, l2};
+        if (seq == 7u) {
+            int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+            for (auto& pm : perm)
+                t[FF + ((size_t)ls[pm[0]] * F + ls[pm[1]]) * F + ls[pm[2]]] = 1;
+        } else {
+            int c = seq == 6u ? 0 : (seq == 5u ? 1 : 2);   // the vertex on both edges
+            int x = (c + 1) % 3, y = (c + 2) % 3;
+            t[((size_t)ls[c] * F + ls[x]) * F + ls[y]] = 1;
+            t[((size_t)ls[c] * F + ls[y]) * F + ls[x]] = 1;
+        }
+    }
+    f3.alloc(t.size());
+    to_device(f3.p, t.data(), t.size());
+}
+
+void Miner::join(int n) {
+    Level& L = lv[n];
+    Level& P = lv[n - 2];
+    L.n = n;
+    const int M = n - 2;
+    const int64_t nwork = P.rows * M;
+    L.st.parents = P.rows;
+    L.st.work_items = nwork;
+    const uint64_t thr =
+        opt.sampling_rate >= 1.0 ? ~0ull
+                                 : (uint64_t)std::ldexp(opt.sampling_rate, 64);
+    auto args = [&](Rec R, int64_t* counts, const int64_t* offsets, int32_t* out, int64_t rows) {
+        JoinArgs a;
+        a.row = frow.p; a.col = fcol.p; a.vf = vf.p;
+        a.npieces = npieces.p; a.leafoff = leafoff.p;
+        a.eset = eset.p; a.emask = emask;
+        a.f3 = f3.p; a.F = F;
+        a.par = P.emb.p; a.padj = P.tab.qadj.p;
+        a.R = R;
+        a.work_ctr = counters.p + 2; a.nwork = nwork;
+        a.emitted = counters.p; a.cands = counters.p + 1; a.bytes = counters.p + 3;
+        a.prune = opt.disable_pruning ? 0 : 1;
+        a.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
+        a.seed = opt.seed; a.sample_thr = thr;
+        a.counts = counts; a.offsets = offsets; a.out = out; a.out_rows = rows;
+        return a;
+    };
+    auto launch_mode = [&](int mode, const JoinArgs& a) {
+#define FSM_JOIN_CASE(NN)                                                           \
+    case NN:                                                                        \
+        if (mode == MODE_DOMAIN) k_join<NN, MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a); \
+        else if (mode == MODE_COUNT) k_join<NN, MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a); \
+        else k_join<NN, MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);            \
+        break;
+        switch (n) {
+            FSM_JOIN_CASE(4)
+            FSM_JOIN_CASE(5)
+            FSM_JOIN_CASE(6)
+            FSM_JOIN_CASE(7)
+            default: fail(FSM_EINVAL, "bad join size %d", n);
+        }
+#undef FSM_JOIN_CASE
+        FSM_LAUNCH_CHECK();
+    };
+    hipEvent_t j0, j1;
+    FSM_HIP(hipEventCreate(&j0));
+    FSM_HIP(hipEventCreate(&j1));
+    try {
+        domain_level(L, [&](Rec R) {
+            FSM_HIP(hipEventRecord(j0, st));
+            if (nwork > 0) launch_mode(MODE_DOMAIN, args(R, nullptr, nullptr, nullptr, 0));
+            FSM_HIP(hipEventRecord(j1, st));
+        });
+        float ms = 0;
+        FSM_HIP(hipEventSynchronize(j1));
+        FSM_HIP(hipEventElapsedTime(&ms, j0, j1));
+        L.st.join_ms = ms;
+    } catch (...) {
+        (void)hipEventDestroy(j0);
+        (void)hipEventDestroy(j1);
+        throw;
+    }
+    (void)hipEventDestroy(j0);
+    (void)hipEventDestroy(j1);
+    if (n + 2 <= opt.max_size) {
+        materialize(L, nwork, [&](int mode, int64_t* counts, const int64_t* offsets, int32_t* out,
+                                  int64_t rows) {
+            if (nwork > 0) launch_mode(mode, args(rec(L), counts, offsets, out, rows));
+        });
+    }
+}
+
+void Miner::emit_results() {
+    for (int n = 2; n <= opt.max_size; ++n) {
+        const int npairs = n * (n - 1) / 2;
+        for (auto& kv : lv[n].freq) {
+            fsm_code c;
+            memset(&c, 0, sizeof(c));
+            c.n = n;
+            for (int i = 0; i < FSM_MAX_SIZE; ++i) c.label[i] = -1;
+            for (int i = 0; i < n; ++i) {
+                int fl = (int)((kv.first >> (21 + 6 * (n - 1 - i))) & 63);
+                c.label[i] = fvalue[(size_t)fl];
+            }
+            uint32_t seq = (uint32_t)(kv.first & ((1u << 21) - 1));
+            for (int k = 0; k < npairs; ++k)
+                if ((seq >> (npairs - 1 - k)) & 1u) c.adj |= 1u << k;
+            res->size.push_back(n);
+            res->code.push_back(c);
+            res->support.push_back(kv.second);
+        }
+    }
+}
+
+void Miner::run() {
+    auto t0 = std::chrono::steady_clock::now();
+    st = stream();
+    res->stats.max_size = opt.max_size;
+    res->stats.dropped_self_loops = g->dropped_loops;
+    res->stats.dropped_duplicates = g->dropped_dups;
+    // frequent labels: a pattern vertex of label l has at most count(l) images
+    std::vector<int32_t> fmap((size_t)g->num_labels, -1);
+    for (int32_t l = 0; l < g->num_labels; ++l)
+        if (g->label_count[(size_t)l] >= opt.support) {
+            if (F >= FSM_MAX_FREQ_LABELS)
+                fail(FSM_EUNSUPPORTED, "more than %d labels occur on >= %lld vertices",
+                     FSM_MAX_FREQ_LABELS, (long long)opt.support);
+            fmap[(size_t)l] = F++;
+            fvalue.push_back(g->label_value[(size_t)l]);
+        }
+    res->stats.frequent_labels = F;
+    if (F == 0 || g->nnz == 0) {
+        res->stats.total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return;
+    }
+    int dev = 0;
+    FSM_HIP(hipGetDevice(&dev));
+    int cus = 0;
+    FSM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    grid_persistent = (unsigned)std::max(1, cus) * 8;
+    DBuf<int32_t> dmap(fmap.size());
+    to_device(dmap.p, fmap.data(), fmap.size());
+    vf.alloc((size_t)g->n);
+    k_vertex_flabel<<<grid_for(g->n, TPB), TPB, 0, st>>>(g->lab.p, g->n, dmap.p, vf.p);
+    FSM_LAUNCH_CHECK();
+    W = (uint32_t)((g->n + 31) / 32);
+    uint64_t want = opt.pool_bytes_min > 0 ? (uint64_t)opt.pool_bytes_min / 4 : (64ull << 20) / 4;
+    want = std::max<uint64_t>(want, (uint64_t)64 * FSM_MAX_SIZE * W);
+    ensure_pool(want);
+    pool_ctr.alloc(1);
+    counters.alloc(4);
+    flags.alloc(1);
+
+    hipEvent_t e0, e1;
+    FSM_HIP(hipEventCreate(&e0));
+    FSM_HIP(hipEventCreate(&e1));
+    auto timed = [&](int n, auto&& body) {
+        FSM_HIP(hipEventRecord(e0, st));
+        body();
+        FSM_HIP(hipEventRecord(e1, st));
+        FSM_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        FSM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        lv[n].st.kernel_ms = ms;
+    };
+    try {
+        timed(2, [&] { level2(); });
+        build_gf();
+        if (opt.max_size >= 3) timed(3, [&] { level3(); });
+        // level-2 embeddings (edges of G_f, u < w) for the size-4 join
+        if (opt.max_size >= 4) {
+            Level& L = lv[2];
+            materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
+                                     int32_t* out, int64_t rows) {
+                L2Args a{frow.p, fcol.p, vf.p, g->n, rec(L), counters.p, counts, offsets, out, rows};
+                if (mode == MODE_COUNT) k_level2<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
+                else k_level2<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
+                FSM_LAUNCH_CHECK();
+            });
+        }
+        if (opt.max_size >= 5) {
+            Level& L = lv[3];
+            materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
+                                     int32_t* out, int64_t rows) {
+                L3Args a{frow.p, fcol.p, vf.p, g->n, eset.p, emask, rec(L), counters.p,
+                         counts, offsets, out, rows};
+                if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
+                else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
+                FSM_LAUNCH_CHECK();
+            });
+        }
+        if (opt.max_size < 4) lv[2].tab = Tables();
+        if (opt.max_size < 5) lv[3].tab = Tables();
+        for (int n = 4; n <= opt.max_size; ++n) {
+            timed(n, [&] { join(n); });
+            // size n-2 embeddings and their QP table are no longer needed,
+            // nor the size-n table when no later join reads it
+            lv[n - 2].emb.reset();
+            lv[n - 2].tab = Tables();
+            if (n + 2 > opt.max_size) lv[n].tab = Tables();
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int n = 2; n <= opt.max_size; ++n) res->stats.level[n] = lv[n].st;
+    emit_results();
+    res->stats.total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r) {
+    Miner m;
+    m.g = g;
+    m.opt = opt;
+    m.res = r;
+    m.run();
+}
+
+}  // namespace fsm

@@ -1,0 +1,167 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function the header declares, validates arguments before any device
+work, and its dissection rule (same source as the device join) meets its
+definition."""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2101_07690_amd as fsm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fsm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert "fsm_build_graph" in names and "fsm_mine" in names
+    L = fsm.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def status_of(exc):
+    return exc.value.code
+
+
+def test_build_graph_rejects_bad_input_before_device_work():
+    with pytest.raises(fsm.FsmError) as e:
+        fsm.Graph(0, [], [], [])
+    assert status_of(e) == -1
+    with pytest.raises(fsm.FsmError) as e:
+        fsm.Graph(3, [0, 1], [1, 3], [0, 0, 0])          # id out of range
+    assert status_of(e) == -1
+    with pytest.raises(fsm.FsmError) as e:
+        fsm.Graph(3, [0], [1], [0, -2, 0])              # negative label
+    assert status_of(e) == -1
+    with pytest.raises(fsm.FsmError) as e:
+        fsm.Graph(2, [0], [1], [0, 1 << 24])             # label too large
+    assert status_of(e) == -1
+
+
+def test_mine_rejects_bad_arguments():
+    import ctypes
+    L = fsm.lib()
+    h = ctypes.c_void_p()
+    assert L.fsm_mine(None, 1, 4, 0, ctypes.byref(h)) == -1
+    assert L.fsm_mine(None, 1, 4, fsm.FSM_SAMPLED, ctypes.byref(h)) == -1
+    assert b"fsm_mine_ex" in L.fsm_last_error()
+    o = fsm.Options()
+    o.support, o.max_size = 0, 4
+    assert L.fsm_mine_ex(None, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert L.fsm_result_count(None) == -1
+    assert L.fsm_graph_vertices(None) == -1
+
+
+def connected(vs, edges):
+    vs = set(vs)
+    if not vs:
+        return False
+    start = next(iter(vs))
+    seen, stack = {start}, [start]
+    while stack:
+        v = stack.pop()
+        for a, b in edges:
+            for x, y in ((a, b), (b, a)):
+                if x == v and y in vs and y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+    return seen == vs
+
+
+def rule_by_definition(ids, edges):
+    """The dissection the join accepts, straight from its definition: the
+    lexicographically smallest sorted id triple l that is connected and has a
+    member v' with (V \\ l) + v' connected; v' the smallest such member."""
+    order = sorted(ids)
+    pos = {v: i for i, v in enumerate(ids)}
+    E = [(ids[a], ids[b]) for a, b in edges]
+    for trip in itertools.combinations(order, 3):
+        if not connected(trip, [e for e in E if e[0] in trip and e[1] in trip]):
+            continue
+        rest = set(ids) - set(trip)
+        for v in trip:
+            part = rest | {v}
+            if connected(part, [e for e in E if e[0] in part and e[1] in part]):
+                return sum(1 << pos[x] for x in trip), pos[v]
+    return None
+
+
+def adj_bits(n, edges):
+    a = 0
+    for i, j in edges:
+        i, j = min(i, j), max(i, j)
+        a |= 1 << (i * n - i * (i + 1) // 2 + (j - i - 1))
+    return a
+
+
+@pytest.mark.parametrize("n", [4, 5])
+def test_dissection_rule_exhaustive(n):
+    # every connected graph on n vertices (Theorem 1: a split always exists),
+    # with a shuffled id assignment, agrees with the definition
+    rng = np.random.default_rng(n)
+    pairs = list(itertools.combinations(range(n), 2))
+    checked = 0
+    for mask in range(1, 1 << len(pairs)):
+        edges = [pairs[k] for k in range(len(pairs)) if mask >> k & 1]
+        if not connected(range(n), edges):
+            continue
+        ids = [int(x) for x in rng.permutation(100)[:n]]
+        got = fsm.dissect(ids, adj_bits(n, edges))
+        assert got == rule_by_definition(ids, edges), (ids, edges)
+        checked += 1
+    assert checked == {4: 38, 5: 728}[n]
+
+
+def test_dissection_rule_sampled_six_seven():
+    rng = np.random.default_rng(11)
+    for n in (6, 7):
+        pairs = list(itertools.combinations(range(n), 2))
+        done = 0
+        while done < 300:
+            mask = int(rng.integers(1, 1 << len(pairs)))
+            edges = [pairs[k] for k in range(len(pairs)) if mask >> k & 1]
+            if not connected(range(n), edges):
+                continue
+            ids = [int(x) for x in rng.permutation(1000)[:n]]
+            assert fsm.dissect(ids, adj_bits(n, edges)) == rule_by_definition(ids, edges)
+            done += 1
+
+
+def test_dissection_double_star():
+    # Edges {0-1, 0-4, 0-5, 1-2, 1-3}: the greedy span of the printed
+    # Algorithm 1 takes the bridge 0-1 first and finds no split; the valid
+    # splits are l={0,4,5} / r={0,1,2,3} and l={1,2,3} / r={0,1,4,5}.
+    ids = [0, 1, 2, 3, 4, 5]
+    edges = [(0, 1), (0, 4), (0, 5), (1, 2), (1, 3)]
+    lm, sh = fsm.dissect(ids, adj_bits(6, edges))
+    assert lm == (1 << 0) | (1 << 4) | (1 << 5) and sh == 0
+
+
+def test_dissection_paper_example():
+    # Section 4.3 worked example (graph of Figure 1): '34257' splits into
+    # l = {2,3,4} and r = {3,5,7}; '37485' into l = {3,4,5} and r = {3,7,8}.
+    G = {(2, 3), (3, 4), (3, 5), (3, 7), (3, 8), (2, 8), (4, 5)}
+
+    def induced(vs):
+        return [(vs.index(a), vs.index(b)) for a, b in G if a in vs and b in vs]
+
+    vs = [3, 4, 2, 7, 5]
+    lm, sh = fsm.dissect(vs, adj_bits(5, induced(vs)))
+    assert {vs[i] for i in range(5) if lm >> i & 1} == {2, 3, 4} and vs[sh] == 3
+    vs = [3, 7, 4, 8, 5]
+    lm, sh = fsm.dissect(vs, adj_bits(5, induced(vs)))
+    assert {vs[i] for i in range(5) if lm >> i & 1} == {3, 4, 5} and vs[sh] == 3
+
+
+def test_dissection_rejects_disconnected():
+    with pytest.raises(fsm.FsmError):
+        fsm.dissect([0, 1, 2, 3], adj_bits(4, [(0, 1), (2, 3)]))
