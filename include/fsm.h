@@ -127,8 +127,8 @@ typedef struct {
     uint64_t seed;            /* FSM_SAMPLED: hash seed */
     int64_t hash_capacity_min;  /* >0: initial quick-pattern table slots
                                    (grown on overflow) */
-    int64_t pool_bytes_min;     /* >0: initial domain-bitmap pool bytes
-                                   (grown on overflow) */
+    int64_t pattern_capacity_min;  /* >0: initial canonical-pattern table
+                                      slots (grown on overflow) */
 } fsm_options;
 
 /* Allocation hooks used for all device memory of later calls (e.g. a

@@ -65,7 +65,7 @@ class Options(ctypes.Structure):
                 ("mode", ctypes.c_uint32), ("disable_pruning", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
-                ("pool_bytes_min", ctypes.c_int64)]
+                ("pattern_capacity_min", ctypes.c_int64)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -82,6 +82,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "paper_2101_07690_amd.build.build()")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+    # soname).  Loading torch first makes the dynamic loader bind this
+    # library to that runtime, so torch streams and allocations are valid
+    # here; loading ours first would give torch a second runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -253,7 +261,7 @@ def _stats_dict(st):
 
 def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
-         hash_capacity_min: int = 0, pool_bytes_min: int = 0) -> Result:
+         hash_capacity_min: int = 0, pattern_capacity_min: int = 0) -> Result:
     """Frequent patterns of sizes 2..max_size with MNI support >= support."""
     o = Options()
     o.support = int(support)
@@ -263,7 +271,7 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
     o.sampling_rate = float(sampling_rate)
     o.seed = int(seed) & ((1 << 64) - 1)
     o.hash_capacity_min = int(hash_capacity_min)
-    o.pool_bytes_min = int(pool_bytes_min)
+    o.pattern_capacity_min = int(pattern_capacity_min)
     h = ctypes.c_void_p()
     _check(lib().fsm_mine_ex(graph.handle, ctypes.byref(o), ctypes.byref(h)))
     return Result(h)

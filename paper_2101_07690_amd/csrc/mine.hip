@@ -18,10 +18,12 @@
 //   value[s] = VALID | FREQ | bitmap region << 21 | 3-bit orbit slot per
 //              position; absent on first sight, then the lane computes the
 //              canonical form itself (deterministic), finds / inserts the
-//              code in the pattern table, allocates the pattern's bitmaps
-//              from a pool on first use (CAS), and publishes the value
-//   bits    -> for each position p: set bit v_p in bitmap (region, slot_p),
-//              reading first and issuing the atomicOr only when unset
+//              code in the pattern table and publishes the value; pattern
+//              slot p owns bitmaps p*n .. p*n+n-1, so no lane allocates
+//   bits    -> for each position p: set bit rank(v_p) in bitmap
+//              (region, slot_p), where rank(v) numbers the vertices of v's
+//              label (a position only ever holds vertices of its label);
+//              read first, atomicOr only when unset
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -40,7 +42,7 @@ constexpr uint64_t FREQ = 1ull << 62;
 constexpr uint64_t REGION_MASK = (1ull << 41) - 1;
 constexpr int JOIN_CHUNK = 4;   // work items fetched per queue access
 
-enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, OVF_POOL = 4, ERR_MISSING = 8, ERR_FILL = 16 };
+enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, ERR_MISSING = 8, ERR_FILL = 16 };
 enum { MODE_DOMAIN = 0, MODE_COUNT = 1, MODE_FILL = 2 };
 enum { PIECE_KC = 0, PIECE_KL = 1, PIECE_TR = 2 };   // k-centre wedge, k-leaf wedge, triangle
 
@@ -61,9 +63,8 @@ struct CodeTab {
 };
 
 struct Pool {
-    uint32_t* words;
-    uint64_t nwords;
-    unsigned long long* ctr;   // words handed out
+    uint32_t* words;           // pattern slot p: bitmaps p*n .. p*n+n-1
+    const int32_t* lrank;      // rank of each vertex among its label's vertices
     uint32_t W;                // words per bitmap
 };
 
@@ -130,29 +131,18 @@ __device__ __noinline__ uint64_t publish_qp(const Rec& R, int64_t s, uint64_t L,
     Canon cn = canonicalize(R.n, L, A);
     int64_t p = ht_probe(R.c.kv, R.c.mask, cn.code, true, R.c.count, R.flags, OVF_CODE);
     if (p < 0) return 0;
-    uint64_t* regp = &R.c.kv[2 * p + 1];
-    uint64_t reg = __hip_atomic_load(regp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (reg == 0) {
-        const unsigned long long need = (unsigned long long)R.n * R.pool.W;
-        unsigned long long base = atomicAdd(R.pool.ctr, need);
-        if (base + need > R.pool.nwords) {
-            atomicOr(R.flags, OVF_POOL);
-            return 0;
-        }
-        unsigned long long mine = base / R.pool.W + 1;
-        unsigned long long prev = atomicCAS((unsigned long long*)regp, 0ull, mine);
-        reg = prev == 0 ? mine : prev;
-    }
     R.c.info[p] = VALID | cn.orbits;
     R.q.adj[s] = A;
     R.q.pat[s] = (int32_t)p;
-    uint64_t val = VALID | ((reg - 1) << 21) | cn.slots;
+    uint64_t val = VALID | ((uint64_t)p * R.n << 21) | cn.slots;
     __hip_atomic_store(&R.q.kv[2 * s + 1], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return val;
 }
 
-__device__ __forceinline__ void set_bit(uint32_t* w, int32_t v) {
-    uint32_t bit = 1u << (v & 31);
+// bit r of the bitmap at `bm`: read first, atomicOr only when unset
+__device__ __forceinline__ void set_bit(uint32_t* bm, int32_t r) {
+    uint32_t* w = bm + (r >> 5);
+    uint32_t bit = 1u << (r & 31);
     if (!(*w & bit)) atomicOr(w, bit);
 }
 
@@ -163,7 +153,7 @@ __device__ __forceinline__ void record_bits(const Rec& R, uint64_t val, const in
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
-        set_bit(base + (uint64_t)slot * R.pool.W + (uint32_t)(v[p] >> 5), v[p]);
+        set_bit(base + (uint64_t)slot * R.pool.W, R.pool.lrank[v[p]]);
     }
 }
 
@@ -223,6 +213,15 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// rank of each vertex among the vertices of its frequent label (any order)
+__global__ void k_label_rank(const int32_t* vf, int64_t n, unsigned* cnt, int32_t* rank) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int l = vf[v];
+        rank[v] = l >= 0 ? (int32_t)atomicAdd(&cnt[l], 1u) : 0;
+    }
 }
 
 __global__ void k_vertex_flabel(const int32_t* lab, int64_t n, const int32_t* fmap, int32_t* vf) {
@@ -736,6 +735,373 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
     }
 }
 
+// ------------------------------------------------------------ join, tiled
+//
+// Domain pass of the join, organised like the column hash tables of
+// Section 4.2: work items (parent p, position i) are grouped by
+// (k = p[i], parent QP, i).  A group's work is |parents| x |pieces at k|;
+// it is cut into tiles of 64 pieces (one per lane, decoded once per tile)
+// by up to TILE_P parents (wave-uniform, looped).  Within a tile the child
+// QP of a lane depends only on the connecting edges, so a two-entry
+// register cache resolves almost every QP lookup, and the bits of the
+// joining vertex and of the piece's two vertices are set once per
+// (lane, QP) per tile; the parent-side bits are tested before being set,
+// and lanes sharing a QP read the same words.
+
+constexpr int TILE_P_MAX = 128;
+
+struct GroupBuild {
+    const int32_t* par;
+    int M;
+    int64_t nwork;
+    uint64_t* kv;       // key, parent count
+    uint64_t mask;
+    int32_t* wslot;     // group-table slot of each work item
+    unsigned* count;    // occupied slots
+    uint32_t* flags;
+    unsigned long long* kpar;   // work items per joining vertex
+};
+
+__device__ __forceinline__ uint64_t group_key(int32_t k, int32_t pq, int i) {
+    return (uint64_t)(uint32_t)k << 32 | (uint64_t)(uint32_t)pq << 3 | (uint64_t)i;
+}
+
+__global__ void k_group_insert(GroupBuild b) {
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < b.nwork;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = w / b.M;
+        const int i = (int)(w - p * b.M);
+        const int32_t* row = b.par + p * (b.M + 1);
+        const uint64_t key = group_key(row[i], row[b.M], i);
+        int64_t s = ht_probe(b.kv, b.mask, key, true, b.count, b.flags, OVF_QP);
+        b.wslot[w] = (int32_t)s;
+        if (s >= 0) atomicAdd((unsigned long long*)&b.kv[2 * s + 1], 1ull);
+        atomicAdd(&b.kpar[row[i]], 1ull);
+    }
+}
+
+__global__ void k_group_flags(const uint64_t* kv, uint64_t slots, int64_t* flag) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x)
+        flag[s] = kv[2 * s] != EMPTY_KEY ? 1 : 0;
+}
+
+// every (k, parent QP, position) sub-group takes a contiguous run of its
+// key's parent range, so a key's parents come in runs of equal QP/position
+__global__ void k_group_place(const uint64_t* kv, uint64_t slots, const int64_t* gid,
+                              unsigned long long* kcursor, unsigned long long* goff) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = kv[2 * s];
+        if (key == EMPTY_KEY) continue;
+        goff[gid[s]] = atomicAdd(&kcursor[(int32_t)(key >> 32)], kv[2 * s + 1]);
+    }
+}
+
+__global__ void k_key_flags(const unsigned long long* kpar, int64_t n, int64_t* flag) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = kpar[v] ? 1 : 0;
+}
+
+__global__ void k_key_compact(const unsigned long long* kpar, const int64_t* kpoff, int64_t n,
+                              const int64_t* kid, int32_t* gk, int64_t* gcnt, int64_t* goff) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t P = (int64_t)kpar[v];
+        if (!P) continue;
+        const int64_t g = kid[v];
+        gk[g] = (int32_t)v;
+        gcnt[g] = P;
+        goff[g] = kpoff[v];
+    }
+}
+
+__global__ void k_key_tiles(const int32_t* gk, const int64_t* gcnt, const int64_t* npieces,
+                            int64_t ngroups, int tile_p, int64_t* tiles) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ngroups;
+         g += (int64_t)gridDim.x * blockDim.x)
+        tiles[g] = ((gcnt[g] + tile_p - 1) / tile_p) * ((npieces[gk[g]] + 63) / 64);
+}
+
+__global__ void k_group_fill(int64_t nwork, int M, const int32_t* wslot, const int64_t* gid,
+                             unsigned long long* cursor, int32_t* glist) {
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nwork;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = gid[wslot[w]];
+        glist[atomicAdd(&cursor[g], 1ull)] = (int32_t)(w / M);
+    }
+}
+
+
+struct TileArgs {
+    const int32_t* row;
+    const int32_t* col;
+    const int32_t* vf;
+    const int64_t* npieces;
+    const int32_t* leafoff;
+    const uint64_t* eset;
+    uint64_t emask;
+    const uint8_t* f3;
+    int F;
+    const int32_t* par;
+    const uint64_t* padj;
+    const int32_t* gk;       // joining vertex of each key group
+    const int64_t* goff;     // its parent range in glist
+    const int64_t* gcnt;
+    const int64_t* toff;     // ngroups + 1 tile offsets
+    int64_t ngroups;
+    int64_t ntiles;
+    int tile_p;              // parents per tile
+    const int32_t* glist;
+    Rec R;
+    unsigned long long* emitted;
+    unsigned long long* cands;
+    unsigned long long* bytes;
+    int prune;
+    int sampled;
+    uint64_t seed;
+    uint64_t sample_thr;
+};
+
+// Two-entry per-lane caches: QP key -> value, and the values whose
+// joining-vertex / piece bits this lane already set in the current tile.
+struct LaneCache {
+    uint64_t k0, v0, k1, v1;   // QP lookups (persist across tiles)
+    uint64_t b0, b1;           // bits done in this tile
+};
+
+template <int N>
+__device__ __forceinline__ int children_tile(const TileArgs& a, const int32_t (&cv)[N],
+                                             const int32_t (&lr)[N], int i,
+                                             uint32_t types, uint32_t ec, uint64_t PA,
+                                             uint64_t L, uint64_t ob, int32_t pslot, int lu,
+                                             int lw, LaneCache& c) {
+    constexpr int M = N - 2;
+    const uint32_t Tstar = (1u << i) | (1u << M) | (1u << (M + 1));
+    const uint32_t kbit = 1u << i;
+    const int lk = lab_at(L, i);
+    int got = 0;
+    for (int t = 0; t < 3; ++t) {
+        if (!((types >> t) & 1u)) continue;
+        uint64_t A0 = add_edge(PA, i, M);
+        if (t == PIECE_KC) A0 = add_edge(A0, i, M + 1);
+        else if (t == PIECE_KL) A0 = add_edge(A0, M, M + 1);
+        else A0 = add_edge(add_edge(A0, i, M + 1), M, M + 1);
+        const uint64_t kbase = (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)t << 30 |
+                               (uint64_t)lu << 24 | (uint64_t)lw << 18;
+        uint32_t sub = ec;
+        for (;;) {
+            uint64_t A = A0;
+            uint32_t cb = 0;
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if ((sub >> (2 * j)) & 1u) { A = add_edge(A, j, M); cb |= 1u << (3 * j + 1); }
+                if ((sub >> (2 * j + 1)) & 1u) { A = add_edge(A, j, M + 1); cb |= 1u << (3 * j + 2); }
+            }
+            if (a.prune && sub) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        if (!((sub >> (2 * j + q)) & 1u) || !ok) continue;
+                        const int cpos = M + q;
+                        const bool kb = (amask(A, i) >> j) & 1u;
+                        const bool kc = (amask(A, i) >> cpos) & 1u;
+                        const int lb = lab_at(L, j), lc = lab_at(L, cpos);
+                        if (kb && kc) ok = f3_at(a.f3, a.F, 1, lk, lb, lc);
+                        else if (kb) ok = f3_at(a.f3, a.F, 0, lb, lk, lc);
+                        else if (kc) ok = f3_at(a.f3, a.F, 0, lc, lk, lb);
+                    }
+                }
+            }
+            if (ok && dissection_is(N, ob, A, Tstar, kbit)) {
+                const uint64_t key = kbase | cb;
+                uint64_t val = 0;
+                if (key == c.k0) {
+                    val = c.v0;
+                } else if (key == c.k1) {
+                    val = c.v1;
+                } else {
+                    int64_t s = ht_probe(a.R.q.kv, a.R.q.mask, key, true, a.R.q.count, a.R.flags,
+                                         OVF_QP);
+                    if (s >= 0) {
+                        val = load_value(&a.R.q.kv[2 * s + 1]);
+                        if (!(val & VALID)) val = publish_qp(a.R, s, L, A);
+                    }
+                    if (val) {
+                        c.k1 = c.k0; c.v1 = c.v0;
+                        c.k0 = key; c.v0 = val;
+                    }
+                }
+                if (val) {
+                    const uint64_t region = (val >> 21) & REGION_MASK;
+                    uint32_t* base = a.R.pool.words + region * a.R.pool.W;
+                    const uint32_t W = a.R.pool.W;
+                    if (val != c.b0 && val != c.b1) {
+#pragma unroll
+                        for (int p = 0; p < N; ++p) {
+                            if (p < M && p != i) continue;
+                            const uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
+                            set_bit(base + (uint64_t)slot * W, lr[p]);
+                        }
+                        c.b1 = c.b0;
+                        c.b0 = val;
+                    }
+#pragma unroll
+                    for (int p = 0; p < M; ++p) {
+                        if (p == i) continue;
+                        const uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
+                        set_bit(base + (uint64_t)slot * W, lr[p]);
+                    }
+                }
+                ++got;
+            }
+            if (!sub) break;
+            sub = (sub - 1) & ec;
+        }
+    }
+    return got;
+}
+
+template <int N>
+__global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
+    constexpr int M = N - 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (TPB / 64);
+    unsigned long long emit = 0, cands = 0, bytes = 0;
+    LaneCache c{EMPTY_KEY, 0, EMPTY_KEY, 0, 0, 0};
+    int64_t g = 0;
+    for (int64_t t = wave_id_global(); t < a.ntiles; t += nw) {
+        // group of tile t: last g with toff[g] <= t (t only grows: gallop)
+        {
+            int64_t step = 1;
+            while (g + step < a.ngroups && a.toff[g + step] <= t) { g += step; step <<= 1; }
+            int64_t lo = g, hi = min(g + step, a.ngroups - 1);
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) >> 1;
+                if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            g = lo;
+        }
+        const int32_t k = a.gk[g];
+        const int64_t P = a.gcnt[g];
+        const int64_t Q = a.npieces[k];
+        const int64_t nqt = (Q + 63) / 64;
+        const int64_t local = t - a.toff[g];
+        const int64_t pt = local / nqt, qt = local - pt * nqt;
+        const int64_t q = qt * 64 + lane;
+        const int32_t rk = a.row[k];
+        const int32_t dk = a.row[k + 1] - rk;
+        const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
+        const int lk = a.vf[k];
+        // this lane's piece
+        int32_t u = -1, w = -1, lru = 0, lrw = 0;
+        uint32_t types = 0;
+        int lu = 0, lw = 0;
+        if (q < Q) {
+            const bool centre = q < ncen;
+            if (centre) {
+                int32_t ia, ib;
+                decode_pair(q, &ia, &ib);
+                u = a.col[rk + ia];
+                w = a.col[rk + ib];
+            } else {
+                const int32_t rr = (int32_t)(q - ncen);
+                int32_t lo = 0, hi = dk - 1;
+                while (lo < hi) {
+                    int32_t mid = (lo + hi + 1) >> 1;
+                    if (a.leafoff[rk + mid] <= rr) lo = mid; else hi = mid - 1;
+                }
+                u = a.col[rk + lo];
+                w = a.col[a.row[u] + (rr - a.leafoff[rk + lo])];
+            }
+            bytes += 4;
+            bool ok = w != k;
+            if (ok && a.sampled && sample_hash(a.seed, N, k, u, w) >= a.sample_thr) ok = false;
+            if (ok) {
+                lu = a.vf[u];
+                lw = a.vf[w];
+                lru = a.R.pool.lrank[u];
+                lrw = a.R.pool.lrank[w];
+                if (centre) {
+                    if (f3_at(a.f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
+                    if (f3_at(a.f3, a.F, 1, lk, lu, lw)) {
+                        bytes += 8;
+                        if (has_edge(a.eset, a.emask, u, w)) types |= 1u << PIECE_TR;
+                    }
+                } else if (f3_at(a.f3, a.F, 0, lu, lk, lw)) {
+                    types |= 1u << PIECE_KL;
+                }
+            }
+        }
+        const int32_t qmin = min(k, min(u, w));
+        const int64_t pb = a.goff[g] + pt * a.tile_p;
+        const int64_t pe = min(a.goff[g] + P, pb + a.tile_p);
+        if (lane == 0) cands += (unsigned long long)((pe - pb) * min((int64_t)64, Q - qt * 64));
+        c.b0 = c.b1 = 0;
+        for (int64_t pp = pb; pp < pe; ++pp) {
+            const int32_t p = a.glist[pp];
+            const int32_t* prow = a.par + (int64_t)p * (M + 1);
+            int32_t cv[N], lr[N];
+            int i = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                cv[j] = prow[j];
+                lr[j] = a.R.pool.lrank[cv[j]];
+                if (cv[j] == k) i = j;
+            }
+            const int32_t pslot = prow[M];
+            const uint64_t PA = a.padj[pslot];
+            int32_t mu = INT_MAX;
+            uint64_t L = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j != i) mu = min(mu, cv[j]);
+                L |= (uint64_t)a.vf[cv[j]] << (6 * j);
+            }
+            if (lane == 0) bytes += 4ull * (M + 1);
+            if (!types) continue;
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
+            // n <= 5: the smallest vertex of every child lies in the accepted
+            // size-3 part (exhaustively true for connected graphs on 4 and 5
+            // vertices), so a piece above min(parent \ k) is rejected
+            if (N <= 5 && qmin > mu) ok = false;
+            if (!ok) continue;
+            cv[M] = u;
+            cv[M + 1] = w;
+            uint32_t ec = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j == i) continue;
+                const bool eu = has_edge(a.eset, a.emask, cv[j], u);
+                const bool ew = has_edge(a.eset, a.emask, cv[j], w);
+                ec |= (eu ? 1u : 0u) << (2 * j);
+                ec |= (ew ? 1u : 0u) << (2 * j + 1);
+            }
+            const uint64_t Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1));
+            const uint64_t ob = rank_bits<N>(cv);
+            lr[M] = lru;
+            lr[M + 1] = lrw;
+            const int got =
+                children_tile<N>(a, cv, lr, i, types, ec, PA, Lc, ob, pslot, lu, lw, c);
+            emit += (unsigned long long)got;
+            bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
+        }
+    }
+    const int64_t te = wave_sum((int64_t)emit);
+    const int64_t tc = wave_sum((int64_t)cands);
+    const int64_t tb = wave_sum((int64_t)bytes);
+    if (lane == 0) {
+        if (te) atomicAdd(a.emitted, (unsigned long long)te);
+        if (tc) atomicAdd(a.cands, (unsigned long long)tc);
+        if (tb) atomicAdd(a.bytes, (unsigned long long)tb);
+    }
+}
+
 // --------------------------------------------------------- MNI reduction
 
 struct MniArgs {
@@ -756,11 +1122,10 @@ __global__ __launch_bounds__(TPB) void k_mni(MniArgs a) {
     for (uint64_t s = blockIdx.x; s < a.slots; s += gridDim.x) {
         const uint64_t key = a.c.kv[2 * s];
         if (key == EMPTY_KEY) continue;
-        const uint64_t reg = a.c.kv[2 * s + 1];
         const uint64_t info = a.c.info[s];
         int64_t best = -1;
-        if (reg != 0 && (info & VALID)) {
-            const uint32_t* base = a.pool.words + (reg - 1) * a.pool.W;
+        if (info & VALID) {
+            const uint32_t* base = a.pool.words + s * a.n * a.pool.W;
             for (int cp = 0; cp < a.n; ++cp) {
                 if ((int)((info >> (3 * cp)) & 7u) != cp) continue;
                 const uint32_t* bm = base + (uint64_t)cp * a.pool.W;
@@ -864,7 +1229,8 @@ struct Miner {
     DBuf<uint8_t> f3;
     DBuf<uint32_t> pool;
     uint64_t pool_words = 0;
-    DBuf<unsigned long long> pool_ctr, counters;   // [emitted, candidates, work queue, bytes]
+    DBuf<int32_t> lrank;
+    DBuf<unsigned long long> counters;   // [emitted, candidates, work queue, bytes]
     DBuf<uint32_t> flags;
     uint32_t W = 1;
     unsigned grid_persistent = 1024;
@@ -880,7 +1246,7 @@ struct Miner {
         Rec R;
         R.q = {L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qpat.p, L.tab.qcount.p};
         R.c = {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
-        R.pool = {pool.p, pool_words, pool_ctr.p, W};
+        R.pool = {pool.p, lrank.p, W};
         R.flags = flags.p;
         R.n = L.n;
         return R;
@@ -897,27 +1263,30 @@ struct Miner {
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
         uint64_t qcap = L.tab.qcap ? L.tab.qcap : qcap0();
-        uint64_t ccap = L.tab.ccap ? L.tab.ccap : (1ull << 12);
+        uint64_t ccap = L.tab.ccap ? L.tab.ccap
+                                   : pow2_at_least((uint64_t)std::max<int64_t>(
+                                         opt.pattern_capacity_min, 1 << 12));
         for (int attempt = 0;; ++attempt) {
             // child keys carry the parent's QP slot in 29 bits
             if (qcap > (1ull << 29))
                 fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
             if (L.tab.qcap != qcap || L.tab.ccap != ccap) L.tab.alloc(qcap, ccap);
             L.tab.reset();
-            pool.zero();
-            pool_ctr.zero();
+            // bitmaps of every pattern slot, zeroed
+            const uint64_t words = ccap * (uint64_t)L.n * W;
+            ensure_pool(words);
+            FSM_HIP(hipMemsetAsync(pool.p, 0, words * sizeof(uint32_t), st));
             counters.zero();
             flags.zero();
             launch(rec(L));
             uint32_t f = scalar_to_host(flags.p);
             if (f & (ERR_MISSING | ERR_FILL))
                 fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", L.n, f);
-            if (!(f & (OVF_QP | OVF_CODE | OVF_POOL))) break;
+            if (!(f & (OVF_QP | OVF_CODE))) break;
             if (attempt >= 8)
                 fail(FSM_EOVERFLOW, "tables kept overflowing at size %d (flags %u)", L.n, f);
             if (f & OVF_QP) qcap *= 16;
             if (f & OVF_CODE) ccap *= 16;
-            if (f & OVF_POOL) ensure_pool(pool_words * 8);
         }
         std::vector<unsigned long long> cnt;
         to_host(cnt, counters.p, 4);
@@ -932,7 +1301,7 @@ struct Miner {
         DBuf<unsigned> on(1);
         on.zero();
         MniArgs m{{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p},
-                  {pool.p, pool_words, pool_ctr.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p,
+                  {pool.p, lrank.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p,
                   npat};
         k_mni<<<grid_for((int64_t)L.tab.ccap, 1, 1u << 16), TPB, 0, st>>>(m);
         FSM_LAUNCH_CHECK();
@@ -969,6 +1338,14 @@ struct Miner {
         if (f) fail(FSM_EDEVICE, "materialisation of size %d failed (flags %u)", L.n, f);
         L.st.stored = total;
     }
+
+    struct Groups {
+        DBuf<int32_t> gk, glist;
+        DBuf<int64_t> goff, gcnt, toff;
+        int64_t ngroups = 0, ntiles = 0;
+        int tile_p = TILE_P_MAX;
+    };
+    void build_groups(const Level& P, int M, int64_t nwork, Groups& G);
 
     void run();
     void level2();
@@ -1057,6 +1434,75 @@ void Miner::level3() {
     to_device(f3.p, t.data(), t.size());
 }
 
+// Group the work items (p, i) of a join by (p[i], parent QP, i) and count
+// the (parents x pieces) tiles of every group.
+void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G) {
+    if (nwork > (int64_t)INT32_MAX * M)
+        fail(FSM_EUNSUPPORTED, "more than 2^31-1 parent embeddings");
+    const int64_t n = g->n;
+    uint64_t cap = pow2_at_least((uint64_t)std::min<int64_t>(nwork, n * 16) * 2 + 16);
+    DBuf<int32_t> wslot((size_t)nwork);
+    DBuf<uint64_t> kv;
+    DBuf<unsigned> cnt(1);
+    DBuf<unsigned long long> kpar((size_t)n);
+    // sub-groups (k, parent QP, position) and per-key work-item counts
+    for (int attempt = 0;; ++attempt) {
+        kv.alloc(2 * cap);
+        k_init_table<<<grid_for((int64_t)cap, TPB), TPB, 0, st>>>(kv.p, cap);
+        FSM_LAUNCH_CHECK();
+        cnt.zero();
+        flags.zero();
+        kpar.zero();
+        GroupBuild b{P.emb.p, M, nwork, kv.p, cap - 1, wslot.p, cnt.p, flags.p, kpar.p};
+        k_group_insert<<<grid_for(nwork, TPB), TPB, 0, st>>>(b);
+        FSM_LAUNCH_CHECK();
+        if (!(scalar_to_host(flags.p) & OVF_QP)) break;
+        if (attempt >= 6) fail(FSM_EOVERFLOW, "join grouping table overflow");
+        cap *= 4;
+    }
+    // parent range of every key, then each sub-group's run inside it
+    DBuf<int64_t> kpoff((size_t)n);
+    scan_exclusive(reinterpret_cast<int64_t*>(kpar.p), kpoff.p, n);
+    DBuf<unsigned long long> kcursor((size_t)n);
+    FSM_HIP(hipMemcpyAsync(kcursor.p, kpoff.p, sizeof(int64_t) * (size_t)n,
+                           hipMemcpyDeviceToDevice, st));
+    DBuf<int64_t> gid(cap);
+    k_group_flags<<<grid_for((int64_t)cap, TPB), TPB, 0, st>>>(kv.p, cap, gid.p);
+    FSM_LAUNCH_CHECK();
+    const int64_t nsub = scan_exclusive(gid.p, gid.p, (int64_t)cap);
+    DBuf<unsigned long long> soff((size_t)std::max<int64_t>(nsub, 1));
+    k_group_place<<<grid_for((int64_t)cap, TPB), TPB, 0, st>>>(kv.p, cap, gid.p, kcursor.p,
+                                                              soff.p);
+    FSM_LAUNCH_CHECK();
+    G.glist.alloc((size_t)nwork);
+    k_group_fill<<<grid_for(nwork, TPB), TPB, 0, st>>>(nwork, M, wslot.p, gid.p, soff.p,
+                                                       G.glist.p);
+    FSM_LAUNCH_CHECK();
+    // key groups = vertices with work, with their tile counts
+    DBuf<int64_t> kid((size_t)n);
+    k_key_flags<<<grid_for(n, TPB), TPB, 0, st>>>(kpar.p, n, kid.p);
+    FSM_LAUNCH_CHECK();
+    G.ngroups = scan_exclusive(kid.p, kid.p, n);
+    const size_t ng = (size_t)std::max<int64_t>(G.ngroups, 1);
+    G.gk.alloc(ng); G.gcnt.alloc(ng); G.goff.alloc(ng); G.toff.alloc(ng + 1);
+    DBuf<int64_t> tiles(ng);
+    k_key_compact<<<grid_for(n, TPB), TPB, 0, st>>>(kpar.p, kpoff.p, n, kid.p, G.gk.p, G.gcnt.p,
+                                                    G.goff.p);
+    FSM_LAUNCH_CHECK();
+    // parents per tile: as many as keep every wave of the grid busy
+    const int64_t want = 16ll * grid_persistent * (TPB / 64);
+    for (G.tile_p = TILE_P_MAX;; G.tile_p /= 2) {
+        k_key_tiles<<<grid_for(G.ngroups, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p,
+                                                              G.ngroups, G.tile_p, tiles.p);
+        FSM_LAUNCH_CHECK();
+        G.ntiles = scan_exclusive(tiles.p, G.toff.p, G.ngroups);
+        if (G.tile_p == 1 || G.ntiles >= want) break;
+    }
+    FSM_HIP(hipMemcpyAsync(G.toff.p + G.ngroups, &G.ntiles, sizeof(int64_t),
+                           hipMemcpyHostToDevice, st));
+    FSM_HIP(hipStreamSynchronize(st));
+}
+
 void Miner::join(int n) {
     Level& L = lv[n];
     Level& P = lv[n - 2];
@@ -1087,8 +1533,7 @@ void Miner::join(int n) {
     auto launch_mode = [&](int mode, const JoinArgs& a) {
 #define FSM_JOIN_CASE(NN)                                                           \
     case NN:                                                                        \
-        if (mode == MODE_DOMAIN) k_join<NN, MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a); \
-        else if (mode == MODE_COUNT) k_join<NN, MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a); \
+        if (mode == MODE_COUNT) k_join<NN, MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a); \
         else k_join<NN, MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);            \
         break;
         switch (n) {
@@ -1101,13 +1546,43 @@ void Miner::join(int n) {
 #undef FSM_JOIN_CASE
         FSM_LAUNCH_CHECK();
     };
+    Groups G;
+    if (nwork > 0) build_groups(P, M, nwork, G);
+    auto tile_args = [&](Rec R) {
+        TileArgs t;
+        t.row = frow.p; t.col = fcol.p; t.vf = vf.p;
+        t.npieces = npieces.p; t.leafoff = leafoff.p;
+        t.eset = eset.p; t.emask = emask;
+        t.f3 = f3.p; t.F = F;
+        t.par = P.emb.p; t.padj = P.tab.qadj.p;
+        t.gk = G.gk.p;
+        t.goff = G.goff.p; t.gcnt = G.gcnt.p; t.toff = G.toff.p;
+        t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p;
+        t.tile_p = G.tile_p;
+        t.R = R;
+        t.emitted = counters.p; t.cands = counters.p + 1; t.bytes = counters.p + 3;
+        t.prune = opt.disable_pruning ? 0 : 1;
+        t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
+        t.seed = opt.seed; t.sample_thr = thr;
+        return t;
+    };
     hipEvent_t j0, j1;
     FSM_HIP(hipEventCreate(&j0));
     FSM_HIP(hipEventCreate(&j1));
     try {
         domain_level(L, [&](Rec R) {
             FSM_HIP(hipEventRecord(j0, st));
-            if (nwork > 0) launch_mode(MODE_DOMAIN, args(R, nullptr, nullptr, nullptr, 0));
+            if (G.ntiles > 0) {
+                const TileArgs t = tile_args(R);
+                switch (n) {
+                    case 4: k_join_tiles<4><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 5: k_join_tiles<5><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 6: k_join_tiles<6><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 7: k_join_tiles<7><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    default: fail(FSM_EINVAL, "bad join size %d", n);
+                }
+                FSM_LAUNCH_CHECK();
+            }
             FSM_HIP(hipEventRecord(j1, st));
         });
         float ms = 0;
@@ -1183,11 +1658,19 @@ void Miner::run() {
     vf.alloc((size_t)g->n);
     k_vertex_flabel<<<grid_for(g->n, TPB), TPB, 0, st>>>(g->lab.p, g->n, dmap.p, vf.p);
     FSM_LAUNCH_CHECK();
-    W = (uint32_t)((g->n + 31) / 32);
-    uint64_t want = opt.pool_bytes_min > 0 ? (uint64_t)opt.pool_bytes_min / 4 : (64ull << 20) / 4;
-    want = std::max<uint64_t>(want, (uint64_t)64 * FSM_MAX_SIZE * W);
-    ensure_pool(want);
-    pool_ctr.alloc(1);
+    // bitmaps are indexed by rank within a label: as many bits as the most
+    // common frequent label has vertices
+    int64_t maxcount = 1;
+    for (int32_t l = 0; l < g->num_labels; ++l)
+        if (fmap[(size_t)l] >= 0) maxcount = std::max(maxcount, g->label_count[(size_t)l]);
+    W = (uint32_t)((maxcount + 31) / 32);
+    lrank.alloc((size_t)g->n);
+    {
+        DBuf<unsigned> lcnt((size_t)F);
+        lcnt.zero();
+        k_label_rank<<<grid_for(g->n, TPB), TPB, 0, st>>>(vf.p, g->n, lcnt.p, lrank.p);
+        FSM_LAUNCH_CHECK();
+    }
     counters.alloc(4);
     flags.alloc(1);
 

@@ -185,7 +185,7 @@ def test_deterministic(er3300):
 def test_small_tables_grow_and_agree(er3300):
     w = er3300
     a = gpu_mine(w["n"], w["src"], w["dst"], w["vertex_labels"], 3, 5,
-                 hash_capacity_min=2, pool_bytes_min=4096)
+                 hash_capacity_min=2, pattern_capacity_min=2)
     assert_same(a.patterns, oracle.mine(w["n"], w["src"], w["dst"], w["vertex_labels"], 3, 5))
 
 
@@ -211,8 +211,8 @@ def test_sampling_is_a_lower_bound(er3300):
     for n, labs, adj, sup in a.patterns:
         assert sup <= exact[(n, labs, adj)]
     # sizes 2 and 3 are never sampled
-    assert [p for p in a.patterns if p[0] <= 3] == \
-        [(k[0], k[1], k[2], v) for k, v in sorted(exact.items()) if k[0] <= 3]
+    assert {(p[0], p[1], p[2]): p[3] for p in a.patterns if p[0] <= 3} == \
+        {k: v for k, v in exact.items() if k[0] <= 3}
 
 
 # ------------------------------------------------------------- edge cases
