@@ -13,17 +13,18 @@
 // embeddings of frequent patterns are compacted by count / scan / fill
 // (Step 4).
 //
-// Recording a subgraph (any level):
-//   QP key  -> open-addressing table slot s (insert by CAS)
-//   value[s] = VALID | FREQ | bitmap region << 21 | 3-bit orbit slot per
-//              position; absent on first sight, then the lane computes the
-//              canonical form itself (deterministic), finds / inserts the
-//              code in the pattern table and publishes the value; pattern
-//              slot p owns bitmaps p*n .. p*n+n-1, so no lane allocates
-//   bits    -> for each position p: set bit rank(v_p) in bitmap
-//              (region, slot_p), where rank(v) numbers the vertices of v's
+// Recording a subgraph (any level), with no canonical form in the loop:
+//   QP key  -> open-addressing table slot s (insert by CAS; the inserting
+//              lane also stores the QP's ordered labels and adjacency)
+//   bits    -> for each position p: set bit rank(v_p) in the bitmap of
+//              (QP slot s, position p); rank(v) numbers the vertices of v's
 //              label (a position only ever holds vertices of its label);
 //              read first, atomicOr only when unset
+// After the pass, one thread per QP computes its canonical form (Section
+// 4.4: one isomorphism computation per quick-pattern group), the QP's
+// position bitmaps are OR-ed into the bitmaps of (pattern, orbit of the
+// position), and the MNI support is the smallest orbit popcount.  The QP
+// value word then holds VALID | FREQ | 3-bit orbit slot per position.
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -50,6 +51,7 @@ struct QPTab {
     uint64_t* kv;      // 2 words per slot: key, value
     uint64_t mask;     // capacity - 1
     uint64_t* adj;     // packed adjacency of the QP's ordered subgraph
+    uint64_t* lab;     // packed labels of the QP's ordered subgraph
     int32_t* pat;      // pattern-table slot
     unsigned* count;   // occupied slots
 };
@@ -63,7 +65,7 @@ struct CodeTab {
 };
 
 struct Pool {
-    uint32_t* words;           // pattern slot p: bitmaps p*n .. p*n+n-1
+    uint32_t* words;           // table slot s owns bitmaps s*n .. s*n+n-1
     const int32_t* lrank;      // rank of each vertex among its label's vertices
     uint32_t W;                // words per bitmap
 };
@@ -120,23 +122,30 @@ __device__ int64_t ht_probe(uint64_t* kv, uint64_t mask, uint64_t key, bool inse
     return -1;
 }
 
-__device__ __forceinline__ uint64_t load_value(uint64_t* p) {
-    uint64_t v = *p;
-    if (!(v & VALID)) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return v;
-}
-
-// First sight of QP slot s: canonical form, pattern slot, bitmap region.
-__device__ __noinline__ uint64_t publish_qp(const Rec& R, int64_t s, uint64_t L, uint64_t A) {
-    Canon cn = canonicalize(R.n, L, A);
-    int64_t p = ht_probe(R.c.kv, R.c.mask, cn.code, true, R.c.count, R.flags, OVF_CODE);
-    if (p < 0) return 0;
-    R.c.info[p] = VALID | cn.orbits;
-    R.q.adj[s] = A;
-    R.q.pat[s] = (int32_t)p;
-    uint64_t val = VALID | ((uint64_t)p * R.n << 21) | cn.slots;
-    __hip_atomic_store(&R.q.kv[2 * s + 1], val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return val;
+// QP slot of `key`, inserting it when new; the inserting lane stores the
+// ordered subgraph (labels L, adjacency A) for the canonical pass.
+__device__ __forceinline__ int64_t qp_slot(const Rec& R, uint64_t key, uint64_t L, uint64_t A) {
+    uint64_t h = mix64(key) & R.q.mask;
+    for (uint64_t i = 0; i <= R.q.mask; ++i) {
+        const uint64_t cur = R.q.kv[2 * h];
+        if (cur == key) return (int64_t)h;
+        if (cur == EMPTY_KEY) {
+            const unsigned long long prev =
+                atomicCAS((unsigned long long*)&R.q.kv[2 * h], (unsigned long long)EMPTY_KEY,
+                          (unsigned long long)key);
+            if (prev == EMPTY_KEY) {
+                R.q.adj[h] = A;
+                R.q.lab[h] = L;
+                const unsigned c = atomicAdd(R.q.count, 1u);
+                if ((uint64_t)c * 2 > R.q.mask) atomicOr(R.flags, OVF_QP);
+                return (int64_t)h;
+            }
+            if (prev == key) return (int64_t)h;
+        }
+        h = (h + 1) & R.q.mask;
+    }
+    atomicOr(R.flags, OVF_QP);
+    return -1;
 }
 
 // bit r of the bitmap at `bm`: read first, atomicOr only when unset
@@ -146,29 +155,15 @@ __device__ __forceinline__ void set_bit(uint32_t* bm, int32_t r) {
     if (!(*w & bit)) atomicOr(w, bit);
 }
 
-template <int N>
-__device__ __forceinline__ void record_bits(const Rec& R, uint64_t val, const int32_t (&v)[N]) {
-    const uint64_t region = (val >> 21) & REGION_MASK;
-    uint32_t* base = R.pool.words + region * R.pool.W;
-#pragma unroll
-    for (int p = 0; p < N; ++p) {
-        uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
-        set_bit(base + (uint64_t)slot * R.pool.W, R.pool.lrank[v[p]]);
-    }
-}
-
 // Domain pass: record one subgraph; returns its QP slot (or -1).
 template <int N>
 __device__ __forceinline__ int64_t record(const Rec& R, uint64_t key, uint64_t L, uint64_t A,
                                           const int32_t (&v)[N]) {
-    int64_t s = ht_probe(R.q.kv, R.q.mask, key, true, R.q.count, R.flags, OVF_QP);
+    const int64_t s = qp_slot(R, key, L, A);
     if (s < 0) return -1;
-    uint64_t val = load_value(&R.q.kv[2 * s + 1]);
-    if (!(val & VALID)) {
-        val = publish_qp(R, s, L, A);
-        if (!val) return -1;
-    }
-    record_bits<N>(R, val, v);
+    uint32_t* base = R.pool.words + (uint64_t)s * N * R.pool.W;
+#pragma unroll
+    for (int p = 0; p < N; ++p) set_bit(base + (uint64_t)p * R.pool.W, R.pool.lrank[v[p]]);
     return s;
 }
 
@@ -547,12 +542,11 @@ __device__ int children(const JoinArgs& a, const int32_t (&cv)[N], int i, uint32
         uint32_t sub = ec;
         for (;;) {
             uint64_t A = A0;
-            uint32_t cb = 0;
             bool ok = true;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                if ((sub >> (2 * j)) & 1u) { A = add_edge(A, j, M); cb |= 1u << (3 * j + 1); }
-                if ((sub >> (2 * j + 1)) & 1u) { A = add_edge(A, j, M + 1); cb |= 1u << (3 * j + 2); }
+                if ((sub >> (2 * j)) & 1u) A = add_edge(A, j, M);
+                if ((sub >> (2 * j + 1)) & 1u) A = add_edge(A, j, M + 1);
             }
             if (a.prune && sub) {
                 // Section 4.5: a size-3 subgraph around the joining vertex k
@@ -573,7 +567,7 @@ __device__ int children(const JoinArgs& a, const int32_t (&cv)[N], int i, uint32
                 }
             }
             if (ok && dissection_is(N, ob, A, Tstar, kbit)) {
-                const uint64_t key = kbase | cb;
+                const uint64_t key = kbase | sub;
                 if (MODE == MODE_DOMAIN) {
                     record<N>(a.R, key, L, A, cv);
                     ++got;
@@ -862,104 +856,171 @@ struct TileArgs {
     int sampled;
     uint64_t seed;
     uint64_t sample_thr;
+    const uint16_t* dtab;    // dissection table of this size
 };
 
-// Two-entry per-lane caches: QP key -> value, and the values whose
+// Two-entry per-lane caches: QP key -> slot, and the QP slots (+1) whose
 // joining-vertex / piece bits this lane already set in the current tile.
 struct LaneCache {
     uint64_t k0, v0, k1, v1;   // QP lookups (persist across tiles)
     uint64_t b0, b1;           // bits done in this tile
 };
 
+// Rank-space pair bit: vertices ordered by id, pair (a, b) of ranks in the
+// row-major upper-triangle order of an N-vertex graph.
+template <int N>
+__device__ __forceinline__ uint32_t rbit(int a, int b) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return 1u << (lo * N - lo * (lo + 1) / 2 + (hi - lo - 1));
+}
+
+// Adjacency of every parent vertex except k with the piece's two new
+// vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  All first probes
+// are issued before any is resolved.
+template <int N>
+__device__ __forceinline__ uint32_t connecting_edges(const uint64_t* eset, uint64_t emask,
+                                                     const int32_t (&cv)[N], int i) {
+    constexpr int M = N - 2;
+    uint64_t key[2 * M], h[2 * M], got[2 * M];
+#pragma unroll
+    for (int b = 0; b < 2 * M; ++b) {
+        const int32_t x = cv[b >> 1], y = cv[M + (b & 1)];
+        key[b] = x < y ? ((uint64_t)(uint32_t)x << 32 | (uint32_t)y)
+                       : ((uint64_t)(uint32_t)y << 32 | (uint32_t)x);
+        h[b] = mix64(key[b]) & emask;
+    }
+#pragma unroll
+    for (int b = 0; b < 2 * M; ++b) got[b] = ((b >> 1) != i) ? eset[h[b]] : EMPTY_KEY;
+    uint32_t ec = 0;
+#pragma unroll
+    for (int b = 0; b < 2 * M; ++b) {
+        if ((b >> 1) == i) continue;
+        uint64_t k = got[b], hh = h[b];
+        while (k != key[b] && k != EMPTY_KEY) {   // load <= 1/4: short chains
+            hh = (hh + 1) & emask;
+            k = eset[hh];
+        }
+        if (k == key[b]) ec |= 1u << b;
+    }
+    return ec;
+}
+
+// All children of one (parent, position, piece) candidate in the domain
+// pass.  The dissection check is a lookup in a table indexed by the child's
+// adjacency with vertices in id order (the rule depends on nothing else);
+// the connecting-edge subsets that the Section 4.5 pruning rejects are
+// excluded from the enumeration up front.
 template <int N>
 __device__ __forceinline__ int children_tile(const TileArgs& a, const int32_t (&cv)[N],
-                                             const int32_t (&lr)[N], int i,
-                                             uint32_t types, uint32_t ec, uint64_t PA,
-                                             uint64_t L, uint64_t ob, int32_t pslot, int lu,
-                                             int lw, LaneCache& c) {
+                                             const int32_t (&lr)[N], int i, uint32_t types,
+                                             uint32_t ec, uint64_t PA, uint64_t L, int32_t pslot,
+                                             int lu, int lw, LaneCache& c) {
     constexpr int M = N - 2;
-    const uint32_t Tstar = (1u << i) | (1u << M) | (1u << (M + 1));
-    const uint32_t kbit = 1u << i;
-    const int lk = lab_at(L, i);
+    int rk[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        int r = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) r += (cv[q] < cv[p]) ? 1 : 0;
+        rk[p] = r;
+    }
+    int rki = 0;
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+        if (p == i) rki = rk[p];
+    uint32_t rpar = 0;
+#pragma unroll
+    for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = p + 1; q < M; ++q)
+            if ((PA >> (8 * p + q)) & 1u) rpar |= rbit<N>(rk[p], rk[q]);
+    const uint32_t eku = rbit<N>(rki, rk[M]), ekw = rbit<N>(rki, rk[M + 1]);
+    const uint32_t euw = rbit<N>(rk[M], rk[M + 1]);
+    uint32_t cm[2 * M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        cm[2 * j] = rbit<N>(rk[j], rk[M]);
+        cm[2 * j + 1] = rbit<N>(rk[j], rk[M + 1]);
+    }
+    const uint32_t want =
+        ((1u << rki) | (1u << rk[M]) | (1u << rk[M + 1])) | ((uint32_t)rki << 8);
+    // connecting edges allowed by the pruning: pieces joined to k by both
+    // new vertices (k-centre wedge, triangle) and k-leaf wedges
+    uint32_t allow_both = ec, allow_kl = ec;
+    if (a.prune && ec) {
+        const int lk = lab_at(L, i);
+#pragma unroll
+        for (int b = 0; b < 2 * M; ++b) {
+            if (!((ec >> b) & 1u)) continue;
+            const int j = b >> 1;
+            const bool kb = (PA >> (8 * i + j)) & 1u;
+            const int lb = lab_at(L, j), lc = (b & 1) ? lw : lu;
+            const bool ok2 = kb ? f3_at(a.f3, a.F, 1, lk, lb, lc) : f3_at(a.f3, a.F, 0, lc, lk, lb);
+            const bool okl = (b & 1) ? (kb ? f3_at(a.f3, a.F, 0, lb, lk, lc) : true) : ok2;
+            if (!ok2) allow_both &= ~(1u << b);
+            if (!okl) allow_kl &= ~(1u << b);
+        }
+    }
     int got = 0;
     for (int t = 0; t < 3; ++t) {
         if (!((types >> t) & 1u)) continue;
-        uint64_t A0 = add_edge(PA, i, M);
-        if (t == PIECE_KC) A0 = add_edge(A0, i, M + 1);
-        else if (t == PIECE_KL) A0 = add_edge(A0, M, M + 1);
-        else A0 = add_edge(add_edge(A0, i, M + 1), M, M + 1);
+        const uint32_t r0 =
+            rpar | eku | (t == PIECE_KC ? ekw : (t == PIECE_KL ? euw : (ekw | euw)));
+        const uint32_t allowed = t == PIECE_KL ? allow_kl : allow_both;
         const uint64_t kbase = (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)t << 30 |
                                (uint64_t)lu << 24 | (uint64_t)lw << 18;
-        uint32_t sub = ec;
+        uint32_t sub = allowed;
         for (;;) {
-            uint64_t A = A0;
-            uint32_t cb = 0;
-            bool ok = true;
+            uint32_t radj = r0;
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                if ((sub >> (2 * j)) & 1u) { A = add_edge(A, j, M); cb |= 1u << (3 * j + 1); }
-                if ((sub >> (2 * j + 1)) & 1u) { A = add_edge(A, j, M + 1); cb |= 1u << (3 * j + 2); }
-            }
-            if (a.prune && sub) {
-#pragma unroll
-                for (int j = 0; j < M; ++j) {
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        if (!((sub >> (2 * j + q)) & 1u) || !ok) continue;
-                        const int cpos = M + q;
-                        const bool kb = (amask(A, i) >> j) & 1u;
-                        const bool kc = (amask(A, i) >> cpos) & 1u;
-                        const int lb = lab_at(L, j), lc = lab_at(L, cpos);
-                        if (kb && kc) ok = f3_at(a.f3, a.F, 1, lk, lb, lc);
-                        else if (kb) ok = f3_at(a.f3, a.F, 0, lb, lk, lc);
-                        else if (kc) ok = f3_at(a.f3, a.F, 0, lc, lk, lb);
-                    }
-                }
-            }
-            if (ok && dissection_is(N, ob, A, Tstar, kbit)) {
-                const uint64_t key = kbase | cb;
-                uint64_t val = 0;
+            for (int b = 0; b < 2 * M; ++b)
+                if ((sub >> b) & 1u) radj |= cm[b];
+            if (a.dtab[radj] == want) {
+                const uint64_t key = kbase | sub;
+                int64_t s;
                 if (key == c.k0) {
-                    val = c.v0;
+                    s = (int64_t)c.v0;
                 } else if (key == c.k1) {
-                    val = c.v1;
+                    s = (int64_t)c.v1;
                 } else {
-                    int64_t s = ht_probe(a.R.q.kv, a.R.q.mask, key, true, a.R.q.count, a.R.flags,
-                                         OVF_QP);
-                    if (s >= 0) {
-                        val = load_value(&a.R.q.kv[2 * s + 1]);
-                        if (!(val & VALID)) val = publish_qp(a.R, s, L, A);
+                    uint64_t A = add_edge(PA, i, M);
+                    if (t == PIECE_KC) A = add_edge(A, i, M + 1);
+                    else if (t == PIECE_KL) A = add_edge(A, M, M + 1);
+                    else A = add_edge(add_edge(A, i, M + 1), M, M + 1);
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        if ((sub >> (2 * j)) & 1u) A = add_edge(A, j, M);
+                        if ((sub >> (2 * j + 1)) & 1u) A = add_edge(A, j, M + 1);
                     }
-                    if (val) {
+                    s = qp_slot(a.R, key, L, A);
+                    if (s >= 0) {
                         c.k1 = c.k0; c.v1 = c.v0;
-                        c.k0 = key; c.v0 = val;
+                        c.k0 = key; c.v0 = (uint64_t)s;
                     }
                 }
-                if (val) {
-                    const uint64_t region = (val >> 21) & REGION_MASK;
-                    uint32_t* base = a.R.pool.words + region * a.R.pool.W;
+                if (s >= 0) {
                     const uint32_t W = a.R.pool.W;
-                    if (val != c.b0 && val != c.b1) {
+                    uint32_t* base = a.R.pool.words + (uint64_t)s * N * W;
+                    // joining vertex and piece vertices: once per QP per tile
+                    if ((uint64_t)s + 1 != c.b0 && (uint64_t)s + 1 != c.b1) {
 #pragma unroll
                         for (int p = 0; p < N; ++p) {
                             if (p < M && p != i) continue;
-                            const uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
-                            set_bit(base + (uint64_t)slot * W, lr[p]);
+                            set_bit(base + (uint64_t)p * W, lr[p]);
                         }
                         c.b1 = c.b0;
-                        c.b0 = val;
+                        c.b0 = (uint64_t)s + 1;
                     }
 #pragma unroll
                     for (int p = 0; p < M; ++p) {
                         if (p == i) continue;
-                        const uint32_t slot = (uint32_t)(val >> (3 * p)) & 7u;
-                        set_bit(base + (uint64_t)slot * W, lr[p]);
+                        set_bit(base + (uint64_t)p * W, lr[p]);
                     }
                 }
                 ++got;
             }
             if (!sub) break;
-            sub = (sub - 1) & ec;
+            sub = (sub - 1) & allowed;
         }
     }
     return got;
@@ -1073,21 +1134,11 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             if (!ok) continue;
             cv[M] = u;
             cv[M + 1] = w;
-            uint32_t ec = 0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-                if (j == i) continue;
-                const bool eu = has_edge(a.eset, a.emask, cv[j], u);
-                const bool ew = has_edge(a.eset, a.emask, cv[j], w);
-                ec |= (eu ? 1u : 0u) << (2 * j);
-                ec |= (ew ? 1u : 0u) << (2 * j + 1);
-            }
+            const uint32_t ec = connecting_edges<N>(a.eset, a.emask, cv, i);
             const uint64_t Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1));
-            const uint64_t ob = rank_bits<N>(cv);
             lr[M] = lru;
             lr[M + 1] = lrw;
-            const int got =
-                children_tile<N>(a, cv, lr, i, types, ec, PA, Lc, ob, pslot, lu, lw, c);
+            const int got = children_tile<N>(a, cv, lr, i, types, ec, PA, Lc, pslot, lu, lw, c);
             emit += (unsigned long long)got;
             bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
         }
@@ -1099,6 +1150,80 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
         if (te) atomicAdd(a.emitted, (unsigned long long)te);
         if (tc) atomicAdd(a.cands, (unsigned long long)tc);
         if (tb) atomicAdd(a.bytes, (unsigned long long)tb);
+    }
+}
+
+// Dissection table of size n: entry x (pair bits of a connected n-vertex
+// graph whose vertex i has the i-th smallest id) = l | v' << 8, the split
+// dissect() picks; 0 for disconnected graphs.
+__global__ void k_dissect_table(int n, uint16_t* tab) {
+    const uint32_t total = 1u << (n * (n - 1) / 2);
+    uint64_t ob = 0;
+    for (int r = 0; r < n; ++r) ob |= (uint64_t)(1u << r) << (8 * r);
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += gridDim.x * blockDim.x) {
+        uint64_t A = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if ((x >> pair_pos(i, j, n)) & 1u) A = add_edge(A, i, j);
+        uint16_t e = 0;
+        if (connected((1u << n) - 1u, A, n)) {
+            uint32_t vb = 0;
+            const uint32_t l = dissect(n, ob, A, &vb);
+            e = (uint16_t)(l | ((uint32_t)__ffs(vb) - 1u) << 8);
+        }
+        tab[x] = e;
+    }
+}
+
+// ------------------------------------------------- canonical patterns
+
+struct CanonArgs {
+    QPTab q;
+    CodeTab c;
+    uint32_t* flags;
+    int n;
+    uint64_t slots;
+};
+
+// One thread per QP: canonical form (the one isomorphism computation of
+// its group), pattern slot, and the orbit slot of each QP position.
+__global__ void k_qp_canon(CanonArgs a) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < a.slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        if (a.q.kv[2 * s] == EMPTY_KEY) continue;
+        const Canon cn = canonicalize(a.n, a.q.lab[s], a.q.adj[s]);
+        const int64_t p = ht_probe(a.c.kv, a.c.mask, cn.code, true, a.c.count, a.flags, OVF_CODE);
+        if (p < 0) continue;
+        a.c.info[p] = VALID | cn.orbits;   // same value from every QP of the pattern
+        a.q.pat[s] = (int32_t)p;
+        a.q.kv[2 * s + 1] = VALID | cn.slots;
+    }
+}
+
+struct MergeArgs {
+    QPTab q;
+    const uint32_t* qbits;     // QP slot s, position p: bitmap s*n+p
+    uint32_t* pbits;           // pattern slot P, orbit slot o: bitmap P*n+o
+    uint32_t W;
+    int n;
+    uint64_t items;            // QP slots * n
+};
+
+// OR every QP position bitmap into its (pattern, orbit) bitmap.
+__global__ __launch_bounds__(TPB) void k_qp_merge(MergeArgs a) {
+    for (uint64_t it = blockIdx.x; it < a.items; it += gridDim.x) {
+        const uint64_t s = it / a.n;
+        const int p = (int)(it - s * a.n);
+        const uint64_t v = a.q.kv[2 * s + 1];
+        if (a.q.kv[2 * s] == EMPTY_KEY || !(v & VALID)) continue;
+        const uint32_t o = (uint32_t)(v >> (3 * p)) & 7u;
+        const uint32_t* src = a.qbits + it * a.W;
+        uint32_t* dst = a.pbits + ((uint64_t)a.q.pat[s] * a.n + o) * a.W;
+        for (uint32_t w = threadIdx.x; w < a.W; w += TPB) {
+            const uint32_t x = src[w];
+            if (x && (dst[w] & x) != x) atomicOr(&dst[w], x);
+        }
     }
 }
 
@@ -1165,7 +1290,7 @@ __global__ void k_mark_frequent(QPTab q, uint64_t slots, const int64_t* sup, int
 // ================================================================== host
 
 struct Tables {
-    DBuf<uint64_t> qkv, qadj, ckv, cinfo;
+    DBuf<uint64_t> qkv, qadj, qlab, ckv, cinfo;
     DBuf<int32_t> qpat;
     DBuf<int64_t> csup;
     DBuf<unsigned> qcount, ccount;
@@ -1176,6 +1301,7 @@ struct Tables {
         ccap = cc;
         qkv.alloc(2 * qc);
         qadj.alloc(qc);
+        qlab.alloc(qc);
         qpat.alloc(qc);
         ckv.alloc(2 * cc);
         cinfo.alloc(cc);
@@ -1183,18 +1309,26 @@ struct Tables {
         qcount.alloc(1);
         ccount.alloc(1);
     }
-    void reset() {
-        hipStream_t st = stream();
-        k_init_table<<<grid_for((int64_t)qcap, TPB), TPB, 0, st>>>(qkv.p, qcap);
-        FSM_LAUNCH_CHECK();
-        k_init_table<<<grid_for((int64_t)ccap, TPB), TPB, 0, st>>>(ckv.p, ccap);
+    void reset_qp() {
+        k_init_table<<<grid_for((int64_t)qcap, TPB), TPB, 0, stream()>>>(qkv.p, qcap);
         FSM_LAUNCH_CHECK();
         qadj.zero();
+        qlab.zero();
         qpat.zero();
+        qcount.zero();
+    }
+    void reset_codes() {
+        k_init_table<<<grid_for((int64_t)ccap, TPB), TPB, 0, stream()>>>(ckv.p, ccap);
+        FSM_LAUNCH_CHECK();
         cinfo.zero();
         csup.zero();
-        qcount.zero();
         ccount.zero();
+    }
+    void alloc_codes(uint64_t cc) {
+        ccap = cc;
+        ckv.alloc(2 * cc);
+        cinfo.alloc(cc);
+        csup.alloc(cc);
     }
 };
 
@@ -1227,8 +1361,8 @@ struct Miner {
     DBuf<int64_t> npieces;
     DBuf<int32_t> leafoff;
     DBuf<uint8_t> f3;
-    DBuf<uint32_t> pool;
-    uint64_t pool_words = 0;
+    DBuf<uint32_t> pool, ppool;     // QP-position bitmaps, pattern-orbit bitmaps
+    uint64_t pool_words = 0, ppool_words = 0;
     DBuf<int32_t> lrank;
     DBuf<unsigned long long> counters;   // [emitted, candidates, work queue, bytes]
     DBuf<uint32_t> flags;
@@ -1238,13 +1372,14 @@ struct Miner {
     fsm_result* res;
 
     uint64_t qcap0() const {
-        uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 16);
+        uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 14);
         return pow2_at_least(c);
     }
 
     Rec rec(Level& L) {
         Rec R;
-        R.q = {L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qpat.p, L.tab.qcount.p};
+        R.q = {L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
+               L.tab.qcount.p};
         R.c = {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
         R.pool = {pool.p, lrank.p, W};
         R.flags = flags.p;
@@ -1252,60 +1387,80 @@ struct Miner {
         return R;
     }
 
-    void ensure_pool(uint64_t words) {
-        if (words <= pool_words) return;
-        pool.alloc(words);
-        pool_words = words;
-    }
-
-    // Run a domain pass with retries on table / pool overflow, then the MNI
-    // reduction; fills L.freq and the FREQ bits.
+    // Run a domain pass (retried with a larger QP table on overflow), then
+    // the canonical pass, the (pattern, orbit) merge and the MNI reduction;
+    // fills L.freq and the FREQ bits of the QP table.
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
         uint64_t qcap = L.tab.qcap ? L.tab.qcap : qcap0();
-        uint64_t ccap = L.tab.ccap ? L.tab.ccap
-                                   : pow2_at_least((uint64_t)std::max<int64_t>(
-                                         opt.pattern_capacity_min, 1 << 12));
         for (int attempt = 0;; ++attempt) {
             // child keys carry the parent's QP slot in 29 bits
             if (qcap > (1ull << 29))
                 fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
-            if (L.tab.qcap != qcap || L.tab.ccap != ccap) L.tab.alloc(qcap, ccap);
-            L.tab.reset();
-            // bitmaps of every pattern slot, zeroed
-            const uint64_t words = ccap * (uint64_t)L.n * W;
-            ensure_pool(words);
+            if (L.tab.qcap != qcap) L.tab.alloc(qcap, 1);
+            L.tab.reset_qp();
+            const uint64_t words = qcap * (uint64_t)L.n * W;
+            if (words > pool_words) {
+                pool.alloc(words);
+                pool_words = words;
+            }
             FSM_HIP(hipMemsetAsync(pool.p, 0, words * sizeof(uint32_t), st));
             counters.zero();
             flags.zero();
             launch(rec(L));
-            uint32_t f = scalar_to_host(flags.p);
+            const uint32_t f = scalar_to_host(flags.p);
             if (f & (ERR_MISSING | ERR_FILL))
                 fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", L.n, f);
-            if (!(f & (OVF_QP | OVF_CODE))) break;
-            if (attempt >= 8)
-                fail(FSM_EOVERFLOW, "tables kept overflowing at size %d (flags %u)", L.n, f);
-            if (f & OVF_QP) qcap *= 16;
-            if (f & OVF_CODE) ccap *= 16;
+            if (!(f & OVF_QP)) break;
+            if (attempt >= 8) fail(FSM_EOVERFLOW, "QP table kept overflowing at size %d", L.n);
+            qcap *= 16;
         }
         std::vector<unsigned long long> cnt;
         to_host(cnt, counters.p, 4);
         L.st.emitted = (int64_t)cnt[0];
         L.st.candidates = (int64_t)cnt[1];
         L.st.algorithmic_bytes = (int64_t)cnt[3];
+        const unsigned nqp = scalar_to_host(L.tab.qcount.p);
+        L.st.quick_patterns = nqp;
+        // canonical forms: pattern table sized for every QP being its own pattern
+        uint64_t ccap = pow2_at_least(std::max<uint64_t>(
+            2ull * nqp + 16, (uint64_t)std::max<int64_t>(opt.pattern_capacity_min, 16)));
+        for (int attempt = 0;; ++attempt) {
+            L.tab.alloc_codes(ccap);
+            L.tab.reset_codes();
+            flags.zero();
+            CanonArgs ca{{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
+                          L.tab.qcount.p},
+                         {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p,
+                          L.tab.ccount.p},
+                         flags.p, L.n, L.tab.qcap};
+            k_qp_canon<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(ca);
+            FSM_LAUNCH_CHECK();
+            if (!(scalar_to_host(flags.p) & OVF_CODE)) break;
+            if (attempt >= 4) fail(FSM_EOVERFLOW, "pattern table overflow at size %d", L.n);
+            ccap *= 4;
+        }
         const unsigned npat = scalar_to_host(L.tab.ccount.p);
-        L.st.quick_patterns = (int64_t)scalar_to_host(L.tab.qcount.p);
         L.st.patterns = npat;
+        const uint64_t pwords = ccap * (uint64_t)L.n * W;
+        if (pwords > ppool_words) {
+            ppool.alloc(pwords);
+            ppool_words = pwords;
+        }
+        FSM_HIP(hipMemsetAsync(ppool.p, 0, pwords * sizeof(uint32_t), st));
+        QPTab q{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
+                L.tab.qcount.p};
+        MergeArgs ma{q, pool.p, ppool.p, W, L.n, L.tab.qcap * (uint64_t)L.n};
+        k_qp_merge<<<grid_for((int64_t)ma.items, 1, 1u << 16), TPB, 0, st>>>(ma);
+        FSM_LAUNCH_CHECK();
         DBuf<uint64_t> okey(npat ? npat : 1);
         DBuf<int64_t> osup(npat ? npat : 1);
         DBuf<unsigned> on(1);
         on.zero();
         MniArgs m{{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p},
-                  {pool.p, lrank.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p,
-                  npat};
+                  {ppool.p, lrank.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
         k_mni<<<grid_for((int64_t)L.tab.ccap, 1, 1u << 16), TPB, 0, st>>>(m);
         FSM_LAUNCH_CHECK();
-        QPTab q{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qpat.p, L.tab.qcount.p};
         k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(q, L.tab.qcap,
                                                                              L.tab.csup.p,
                                                                              opt.support);
@@ -1548,6 +1703,10 @@ void Miner::join(int n) {
     };
     Groups G;
     if (nwork > 0) build_groups(P, M, nwork, G);
+    const uint32_t dsize = 1u << (n * (n - 1) / 2);
+    DBuf<uint16_t> dtab(dsize);
+    k_dissect_table<<<grid_for(dsize, TPB), TPB, 0, st>>>(n, dtab.p);
+    FSM_LAUNCH_CHECK();
     auto tile_args = [&](Rec R) {
         TileArgs t;
         t.row = frow.p; t.col = fcol.p; t.vf = vf.p;
@@ -1564,6 +1723,7 @@ void Miner::join(int n) {
         t.prune = opt.disable_pruning ? 0 : 1;
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
         t.seed = opt.seed; t.sample_thr = thr;
+        t.dtab = dtab.p;
         return t;
     };
     hipEvent_t j0, j1;
