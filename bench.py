@@ -29,6 +29,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after timing, run one elementwise int32 kernel that reads and "
+                         "writes this many MiB (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -57,6 +60,13 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"[bench] {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    if args.copy_mib > 0:
+        a = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.add(a, 1, out=b)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration kernel: read {args.copy_mib} MiB, wrote {args.copy_mib} MiB",
+              file=sys.stderr, flush=True)
     ref = results[0]
     for r in results[1:]:
         assert r.patterns == ref.patterns, "results differ between steps"

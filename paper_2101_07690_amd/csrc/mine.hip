@@ -177,21 +177,35 @@ __device__ __forceinline__ int64_t frequent_slot(const Rec& R, uint64_t key) {
     return (R.q.kv[2 * s + 1] & FREQ) ? s : -1;
 }
 
-__device__ __forceinline__ bool has_edge(const uint64_t* eset, uint64_t emask, int32_t a,
-                                         int32_t b) {
-    uint64_t key = a < b ? ((uint64_t)(uint32_t)a << 32 | (uint32_t)b)
-                         : ((uint64_t)(uint32_t)b << 32 | (uint32_t)a);
-    uint64_t h = mix64(key) & emask;
-    for (;;) {   // load <= 1/4, so an empty slot ends every probe
-        uint64_t k = eset[h];
-        if (k == key) return true;
-        if (k == EMPTY_KEY) return false;
-        h = (h + 1) & emask;
+// Adjacency test through per-vertex neighbour hash tables: vertex b owns a
+// linear-probing table of its G_f neighbours, pow2 slots >= 2*deg(b), at
+// tab[off[b] .. off[b+1]), empty slots -1.  A wave probing one vertex b for
+// many x stays within b's table (a few cache lines).
+struct NbrHash {
+    const uint32_t* off;   // n + 1
+    const int32_t* tab;
+};
+
+__device__ __forceinline__ uint32_t nbr_hash(int32_t x) {
+    uint32_t h = (uint32_t)x * 0x9E3779B1u;
+    return h ^ (h >> 15);
+}
+
+__device__ __forceinline__ bool has_edge(const NbrHash& H, int32_t b, int32_t x) {
+    const uint32_t o = H.off[b], cap = H.off[b + 1] - o;
+    if (!cap) return false;
+    uint32_t h = nbr_hash(x) & (cap - 1);
+    for (;;) {   // load <= 1/2: an empty slot ends every probe
+        const int32_t v = H.tab[o + h];
+        if (v == x) return true;
+        if (v < 0) return false;
+        h = (h + 1) & (cap - 1);
     }
 }
 
+// wave index, kept in a scalar register so wave-uniform work stays scalar
 __device__ __forceinline__ int wave_id_global() {
-    return (int)(blockIdx.x * (TPB / 64) + (threadIdx.x >> 6));
+    return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (TPB / 64) + (threadIdx.x >> 6)));
 }
 
 // ------------------------------------------------------------- setup kernels
@@ -217,6 +231,12 @@ __global__ void k_label_rank(const int32_t* vf, int64_t n, unsigned* cnt, int32_
         const int l = vf[v];
         rank[v] = l >= 0 ? (int32_t)atomicAdd(&cnt[l], 1u) : 0;
     }
+}
+
+__global__ void k_vinfo(const int32_t* vf, const int32_t* rank, int64_t n, uint32_t* vinfo) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        vinfo[v] = vf[v] >= 0 ? ((uint32_t)vf[v] << 26 | (uint32_t)rank[v]) : 0xffffffffu;
 }
 
 __global__ void k_vertex_flabel(const int32_t* lab, int64_t n, const int32_t* fmap, int32_t* vf) {
@@ -260,22 +280,34 @@ __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t*
     }
 }
 
-__global__ void k_eset_insert(const int32_t* row, const int32_t* col, int64_t n, uint64_t* eset,
-                              uint64_t emask) {
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
-         u += (int64_t)gridDim.x * blockDim.x) {
-        for (int32_t e = row[u]; e < row[u + 1]; ++e) {
-            int32_t w = col[e];
-            if (w <= u) continue;
-            uint64_t key = (uint64_t)(uint32_t)u << 32 | (uint32_t)w;
-            uint64_t h = mix64(key) & emask;
-            for (;;) {
-                unsigned long long prev = atomicCAS((unsigned long long*)&eset[h],
-                                                    (unsigned long long)EMPTY_KEY,
-                                                    (unsigned long long)key);
-                if (prev == EMPTY_KEY || prev == key) break;
-                h = (h + 1) & emask;
-            }
+// neighbour-table sizes: pow2 >= 2*deg, 0 for isolated vertices
+__global__ void k_nbr_sizes(const int32_t* row, int64_t n, int64_t* cap) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = row[v + 1] - row[v];
+        int64_t c = 0;
+        if (d > 0) {
+            c = 1;
+            while (c < 2 * d) c <<= 1;
+        }
+        cap[v] = c;
+    }
+}
+
+__global__ void k_nbr_fill(const int32_t* row, const int32_t* col, int64_t n, const int64_t* off,
+                           int64_t total, uint32_t* off32, int32_t* tab) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        if (v == n) { off32[n] = (uint32_t)total; continue; }
+        const int64_t o = off[v];
+        off32[v] = (uint32_t)o;
+        const uint32_t cap = (uint32_t)((v + 1 < n ? off[v + 1] : total) - o);
+        for (uint32_t s = 0; s < cap; ++s) tab[o + s] = -1;
+        for (int32_t e = row[v]; e < row[v + 1]; ++e) {
+            const int32_t x = col[e];
+            uint32_t h = nbr_hash(x) & (cap - 1);
+            while (tab[o + h] >= 0) h = (h + 1) & (cap - 1);
+            tab[o + h] = x;
         }
     }
 }
@@ -374,8 +406,7 @@ struct L3Args {
     const int32_t* col;
     const int32_t* vf;
     int64_t n;
-    const uint64_t* eset;
-    uint64_t emask;
+    NbrHash nh;
     Rec R;
     unsigned long long* emitted;
     int64_t* counts;
@@ -424,7 +455,7 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
                 w = a.col[rb + ib];
                 lu = a.vf[u];
                 lw = a.vf[w];
-                tri = c < u && has_edge(a.eset, a.emask, u, w);
+                tri = c < u && has_edge(a.nh, u, w);
             }
             const uint64_t L = (uint64_t)lc | (uint64_t)lu << 6 | (uint64_t)lw << 12;
             const uint64_t kw = (uint64_t)lc << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
@@ -482,8 +513,7 @@ struct JoinArgs {
     const int32_t* vf;
     const int64_t* npieces;
     const int32_t* leafoff;
-    const uint64_t* eset;
-    uint64_t emask;
+    NbrHash nh;
     const uint8_t* f3;       // [2][F][F][F]: 0 wedge (centre first), 1 triangle
     int F;
     const int32_t* par;      // parents, rows of (M vertices, QP slot)
@@ -672,7 +702,7 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                             if (f3_at(a.f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
                             if (f3_at(a.f3, a.F, 1, lk, lu, lw)) {
                                 bytes += 8;
-                                if (has_edge(a.eset, a.emask, u, w)) types |= 1u << PIECE_TR;
+                                if (has_edge(a.nh, u, w)) types |= 1u << PIECE_TR;
                             }
                         } else {
                             if (f3_at(a.f3, a.F, 0, lu, lk, lw)) types |= 1u << PIECE_KL;
@@ -692,8 +722,8 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
 #pragma unroll
                     for (int j = 0; j < M; ++j) {
                         if (j == i) continue;
-                        if (has_edge(a.eset, a.emask, cv[j], u)) ec |= 1u << (2 * j);
-                        if (has_edge(a.eset, a.emask, cv[j], w)) ec |= 1u << (2 * j + 1);
+                        if (has_edge(a.nh, cv[j], u)) ec |= 1u << (2 * j);
+                        if (has_edge(a.nh, cv[j], w)) ec |= 1u << (2 * j + 1);
                     }
                     ob = rank_bits<N>(cv);
                     got = children<N, MODE, 0>(a, cv, i, types, ec, PA, Lc, ob, pslot, lu, lw,
@@ -828,16 +858,19 @@ __global__ void k_group_fill(int64_t nwork, int M, const int32_t* wslot, const i
 }
 
 
+// Kernel state is kept small (scalar registers are scarce in the loop):
+// vertex label and label rank share one word, and the QP-table insert path
+// reads its pointers through `rec` (device memory) only when it runs.
 struct TileArgs {
     const int32_t* row;
     const int32_t* col;
-    const int32_t* vf;
+    const uint32_t* vinfo;   // frequent label << 26 | rank within the label
     const int64_t* npieces;
     const int32_t* leafoff;
-    const uint64_t* eset;
-    uint64_t emask;
+    NbrHash nh;
     const uint8_t* f3;
     int F;
+    int tile_p;              // parents per tile
     const int32_t* par;
     const uint64_t* padj;
     const int32_t* gk;       // joining vertex of each key group
@@ -846,18 +879,19 @@ struct TileArgs {
     const int64_t* toff;     // ngroups + 1 tile offsets
     int64_t ngroups;
     int64_t ntiles;
-    int tile_p;              // parents per tile
     const int32_t* glist;
-    Rec R;
-    unsigned long long* emitted;
-    unsigned long long* cands;
-    unsigned long long* bytes;
+    const uint16_t* dtab;    // dissection table of this size
+    uint32_t* bits;          // QP-position bitmaps
+    uint32_t W;
     int prune;
+    const Rec* rec;          // QP table (insert path)
+    unsigned long long* ctr; // [emitted, candidates, -, bytes]
     int sampled;
     uint64_t seed;
     uint64_t sample_thr;
-    const uint16_t* dtab;    // dissection table of this size
 };
+
+constexpr uint32_t RANK_MASK = (1u << 26) - 1;
 
 // Two-entry per-lane caches: QP key -> slot, and the QP slots (+1) whose
 // joining-vertex / piece bits this lane already set in the current tile.
@@ -875,32 +909,39 @@ __device__ __forceinline__ uint32_t rbit(int a, int b) {
 }
 
 // Adjacency of every parent vertex except k with the piece's two new
-// vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  All first probes
-// are issued before any is resolved.
+// vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  The parent vertex
+// is the same across the wave, so all lanes probe the same small table; the
+// first probes are issued before any is resolved.
 template <int N>
-__device__ __forceinline__ uint32_t connecting_edges(const uint64_t* eset, uint64_t emask,
-                                                     const int32_t (&cv)[N], int i) {
+__device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int32_t (&cv)[N],
+                                                     int i) {
     constexpr int M = N - 2;
-    uint64_t key[2 * M], h[2 * M], got[2 * M];
+    uint32_t o[M], cap[M], h[2 * M];
+    int32_t got[2 * M];
 #pragma unroll
-    for (int b = 0; b < 2 * M; ++b) {
-        const int32_t x = cv[b >> 1], y = cv[M + (b & 1)];
-        key[b] = x < y ? ((uint64_t)(uint32_t)x << 32 | (uint32_t)y)
-                       : ((uint64_t)(uint32_t)y << 32 | (uint32_t)x);
-        h[b] = mix64(key[b]) & emask;
+    for (int j = 0; j < M; ++j) {
+        o[j] = H.off[cv[j]];
+        cap[j] = H.off[cv[j] + 1] - o[j];
     }
 #pragma unroll
-    for (int b = 0; b < 2 * M; ++b) got[b] = ((b >> 1) != i) ? eset[h[b]] : EMPTY_KEY;
+    for (int b = 0; b < 2 * M; ++b) {
+        const int j = b >> 1;
+        h[b] = nbr_hash(cv[M + (b & 1)]) & (cap[j] - 1);
+        got[b] = (j != i && cap[j]) ? H.tab[o[j] + h[b]] : -1;
+    }
     uint32_t ec = 0;
 #pragma unroll
     for (int b = 0; b < 2 * M; ++b) {
-        if ((b >> 1) == i) continue;
-        uint64_t k = got[b], hh = h[b];
-        while (k != key[b] && k != EMPTY_KEY) {   // load <= 1/4: short chains
-            hh = (hh + 1) & emask;
-            k = eset[hh];
+        const int j = b >> 1;
+        if (j == i) continue;
+        const int32_t x = cv[M + (b & 1)];
+        int32_t v = got[b];
+        uint32_t hh = h[b];
+        while (v >= 0 && v != x) {
+            hh = (hh + 1) & (cap[j] - 1);
+            v = H.tab[o[j] + hh];
         }
-        if (k == key[b]) ec |= 1u << b;
+        if (v == x) ec |= 1u << b;
     }
     return ec;
 }
@@ -992,15 +1033,15 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const int32_t (&
                         if ((sub >> (2 * j)) & 1u) A = add_edge(A, j, M);
                         if ((sub >> (2 * j + 1)) & 1u) A = add_edge(A, j, M + 1);
                     }
-                    s = qp_slot(a.R, key, L, A);
+                    s = qp_slot(*a.rec, key, L, A);
                     if (s >= 0) {
                         c.k1 = c.k0; c.v1 = c.v0;
                         c.k0 = key; c.v0 = (uint64_t)s;
                     }
                 }
                 if (s >= 0) {
-                    const uint32_t W = a.R.pool.W;
-                    uint32_t* base = a.R.pool.words + (uint64_t)s * N * W;
+                    const uint32_t W = a.W;
+                    uint32_t* base = a.bits + (uint64_t)s * N * W;
                     // joining vertex and piece vertices: once per QP per tile
                     if ((uint64_t)s + 1 != c.b0 && (uint64_t)s + 1 != c.b1) {
 #pragma unroll
@@ -1047,7 +1088,6 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             g = lo;
         }
         const int32_t k = a.gk[g];
-        const int64_t P = a.gcnt[g];
         const int64_t Q = a.npieces[k];
         const int64_t nqt = (Q + 63) / 64;
         const int64_t local = t - a.toff[g];
@@ -1056,7 +1096,7 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
         const int32_t rk = a.row[k];
         const int32_t dk = a.row[k + 1] - rk;
         const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
-        const int lk = a.vf[k];
+        const int lk = (int)(a.vinfo[k] >> 26);
         // this lane's piece
         int32_t u = -1, w = -1, lru = 0, lrw = 0;
         uint32_t types = 0;
@@ -1082,15 +1122,16 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             bool ok = w != k;
             if (ok && a.sampled && sample_hash(a.seed, N, k, u, w) >= a.sample_thr) ok = false;
             if (ok) {
-                lu = a.vf[u];
-                lw = a.vf[w];
-                lru = a.R.pool.lrank[u];
-                lrw = a.R.pool.lrank[w];
+                const uint32_t iu = a.vinfo[u], iw = a.vinfo[w];
+                lu = (int)(iu >> 26);
+                lw = (int)(iw >> 26);
+                lru = (int32_t)(iu & RANK_MASK);
+                lrw = (int32_t)(iw & RANK_MASK);
                 if (centre) {
                     if (f3_at(a.f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
                     if (f3_at(a.f3, a.F, 1, lk, lu, lw)) {
                         bytes += 8;
-                        if (has_edge(a.eset, a.emask, u, w)) types |= 1u << PIECE_TR;
+                        if (has_edge(a.nh, u, w)) types |= 1u << PIECE_TR;
                     }
                 } else if (f3_at(a.f3, a.F, 0, lu, lk, lw)) {
                     types |= 1u << PIECE_KL;
@@ -1098,29 +1139,27 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             }
         }
         const int32_t qmin = min(k, min(u, w));
-        const int64_t pb = a.goff[g] + pt * a.tile_p;
-        const int64_t pe = min(a.goff[g] + P, pb + a.tile_p);
-        if (lane == 0) cands += (unsigned long long)((pe - pb) * min((int64_t)64, Q - qt * 64));
+        const int32_t pb = (int32_t)(a.goff[g] + pt * a.tile_p);
+        const int32_t pe = (int32_t)min(a.goff[g] + a.gcnt[g], (int64_t)pb + a.tile_p);
+        if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
         c.b0 = c.b1 = 0;
-        for (int64_t pp = pb; pp < pe; ++pp) {
-            const int32_t p = a.glist[pp];
-            const int32_t* prow = a.par + (int64_t)p * (M + 1);
+        for (int32_t pp = pb; pp < pe; ++pp) {
+            const int32_t* prow = a.par + (int64_t)a.glist[pp] * (M + 1);
             int32_t cv[N], lr[N];
             int i = 0;
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-                cv[j] = prow[j];
-                lr[j] = a.R.pool.lrank[cv[j]];
-                if (cv[j] == k) i = j;
-            }
-            const int32_t pslot = prow[M];
-            const uint64_t PA = a.padj[pslot];
             int32_t mu = INT_MAX;
             uint64_t L = 0;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
+                cv[j] = prow[j];
+                if (cv[j] == k) i = j;
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const uint32_t vi = a.vinfo[cv[j]];
+                lr[j] = (int32_t)(vi & RANK_MASK);
+                L |= (uint64_t)(vi >> 26) << (6 * j);
                 if (j != i) mu = min(mu, cv[j]);
-                L |= (uint64_t)a.vf[cv[j]] << (6 * j);
             }
             if (lane == 0) bytes += 4ull * (M + 1);
             if (!types) continue;
@@ -1132,9 +1171,11 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             // vertices), so a piece above min(parent \ k) is rejected
             if (N <= 5 && qmin > mu) ok = false;
             if (!ok) continue;
+            const int32_t pslot = prow[M];
+            const uint64_t PA = a.padj[pslot];
             cv[M] = u;
             cv[M + 1] = w;
-            const uint32_t ec = connecting_edges<N>(a.eset, a.emask, cv, i);
+            const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
             const uint64_t Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1));
             lr[M] = lru;
             lr[M + 1] = lrw;
@@ -1147,9 +1188,9 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
     const int64_t tc = wave_sum((int64_t)cands);
     const int64_t tb = wave_sum((int64_t)bytes);
     if (lane == 0) {
-        if (te) atomicAdd(a.emitted, (unsigned long long)te);
-        if (tc) atomicAdd(a.cands, (unsigned long long)tc);
-        if (tb) atomicAdd(a.bytes, (unsigned long long)tb);
+        if (te) atomicAdd(&a.ctr[0], (unsigned long long)te);
+        if (tc) atomicAdd(&a.ctr[1], (unsigned long long)tc);
+        if (tb) atomicAdd(&a.ctr[3], (unsigned long long)tb);
     }
 }
 
@@ -1356,14 +1397,18 @@ struct Miner {
     DBuf<int32_t> vf;                     // frequent id per vertex or -1
     DBuf<int32_t> frow, fcol;             // G_f
     int64_t fnnz = 0;
-    DBuf<uint64_t> eset;
-    uint64_t emask = 0;
+    DBuf<uint32_t> nhoff;
+    DBuf<int32_t> nhtab;
+    NbrHash nh() const { return NbrHash{nhoff.p, nhtab.p}; }
     DBuf<int64_t> npieces;
     DBuf<int32_t> leafoff;
     DBuf<uint8_t> f3;
     DBuf<uint32_t> pool, ppool;     // QP-position bitmaps, pattern-orbit bitmaps
     uint64_t pool_words = 0, ppool_words = 0;
     DBuf<int32_t> lrank;
+    DBuf<uint32_t> vinfo;
+    DBuf<Rec> drec;     // device copy of the recording context of the join
+    Rec hrec{};
     DBuf<unsigned long long> counters;   // [emitted, candidates, work queue, bytes]
     DBuf<uint32_t> flags;
     uint32_t W = 1;
@@ -1540,14 +1585,21 @@ void Miner::build_gf() {
     k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row.p, g->col.p, vf.p, n, df2.p, F, cnt.p,
                                                      fnnz, frow.p, fcol.p);
     FSM_LAUNCH_CHECK();
-    // edge set (load <= 1/4) and per-vertex piece counts
-    uint64_t ecap = pow2_at_least((uint64_t)(fnnz / 2) * 4 + 16);
-    eset.alloc(ecap);
-    emask = ecap - 1;
-    k_fill_u64<<<grid_for((int64_t)ecap, TPB), TPB, 0, st>>>(eset.p, ecap, EMPTY_KEY);
-    FSM_LAUNCH_CHECK();
-    k_eset_insert<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, eset.p, emask);
-    FSM_LAUNCH_CHECK();
+    // per-vertex neighbour hash tables (load <= 1/2) and piece counts
+    {
+        DBuf<int64_t> cap((size_t)n + 1);
+        k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, n, cap.p);
+        FSM_LAUNCH_CHECK();
+        const int64_t total = scan_exclusive(cap.p, cap.p, n);
+        if (total >= (int64_t)UINT32_MAX)
+            fail(FSM_EUNSUPPORTED, "neighbour tables exceed 2^32 slots");
+        nhoff.alloc((size_t)n + 1);
+        nhtab.alloc((size_t)(total > 0 ? total : 1));
+        k_nbr_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, cap.p, total, nhoff.p,
+                                                         nhtab.p);
+        FSM_LAUNCH_CHECK();
+        FSM_HIP(hipStreamSynchronize(st));
+    }
     npieces.alloc((size_t)n);
     leafoff.alloc((size_t)(fnnz > 0 ? fnnz : 1));
     k_pieces<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, npieces.p, leafoff.p);
@@ -1559,7 +1611,7 @@ void Miner::level3() {
     Level& L = lv[3];
     L.n = 3;
     auto launch = [&](Rec R) {
-        L3Args a{frow.p, fcol.p, vf.p, g->n, eset.p, emask, R, counters.p,
+        L3Args a{frow.p, fcol.p, vf.p, g->n, nh(), R, counters.p,
                  nullptr, nullptr, nullptr, 0};
         k_level3<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
         FSM_LAUNCH_CHECK();
@@ -1673,7 +1725,7 @@ void Miner::join(int n) {
         JoinArgs a;
         a.row = frow.p; a.col = fcol.p; a.vf = vf.p;
         a.npieces = npieces.p; a.leafoff = leafoff.p;
-        a.eset = eset.p; a.emask = emask;
+        a.nh = nh();
         a.f3 = f3.p; a.F = F;
         a.par = P.emb.p; a.padj = P.tab.qadj.p;
         a.R = R;
@@ -1708,18 +1760,20 @@ void Miner::join(int n) {
     k_dissect_table<<<grid_for(dsize, TPB), TPB, 0, st>>>(n, dtab.p);
     FSM_LAUNCH_CHECK();
     auto tile_args = [&](Rec R) {
+        hrec = R;
+        FSM_HIP(hipMemcpyAsync(drec.p, &hrec, sizeof(Rec), hipMemcpyHostToDevice, st));
         TileArgs t;
-        t.row = frow.p; t.col = fcol.p; t.vf = vf.p;
+        t.row = frow.p; t.col = fcol.p; t.vinfo = vinfo.p;
         t.npieces = npieces.p; t.leafoff = leafoff.p;
-        t.eset = eset.p; t.emask = emask;
+        t.nh = nh();
         t.f3 = f3.p; t.F = F;
         t.par = P.emb.p; t.padj = P.tab.qadj.p;
         t.gk = G.gk.p;
         t.goff = G.goff.p; t.gcnt = G.gcnt.p; t.toff = G.toff.p;
         t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p;
         t.tile_p = G.tile_p;
-        t.R = R;
-        t.emitted = counters.p; t.cands = counters.p + 1; t.bytes = counters.p + 3;
+        t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p;
+        t.ctr = counters.p;
         t.prune = opt.disable_pruning ? 0 : 1;
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
         t.seed = opt.seed; t.sample_thr = thr;
@@ -1831,6 +1885,12 @@ void Miner::run() {
         k_label_rank<<<grid_for(g->n, TPB), TPB, 0, st>>>(vf.p, g->n, lcnt.p, lrank.p);
         FSM_LAUNCH_CHECK();
     }
+    if (maxcount > (int64_t)RANK_MASK)
+        fail(FSM_EUNSUPPORTED, "a frequent label has more than 2^26 vertices");
+    vinfo.alloc((size_t)g->n);
+    k_vinfo<<<grid_for(g->n, TPB), TPB, 0, st>>>(vf.p, lrank.p, g->n, vinfo.p);
+    FSM_LAUNCH_CHECK();
+    drec.alloc(1);
     counters.alloc(4);
     flags.alloc(1);
 
@@ -1865,7 +1925,7 @@ void Miner::run() {
             Level& L = lv[3];
             materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
                                      int32_t* out, int64_t rows) {
-                L3Args a{frow.p, fcol.p, vf.p, g->n, eset.p, emask, rec(L), counters.p,
+                L3Args a{frow.p, fcol.p, vf.p, g->n, nh(), rec(L), counters.p,
                          counts, offsets, out, rows};
                 if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
                 else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
