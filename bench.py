@@ -20,6 +20,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# gfx950 vector issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz; a wave64
+# VALU instruction occupies a SIMD for 4 cycles
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+KERNEL_SOURCES = ("paper_2101_07690_amd/csrc/mine.hip", "paper_2101_07690_amd/csrc/common.h")
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_counters(size, workload):
+    """Counter summary of the dominant kernel from profiles/, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"k_join_tiles{size}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("Kernel sources sha256[:16]"):
+                vals["hash"] = line.split(":")[-1].strip()
+            elif line.startswith("| SQ_") and "|" in line[2:]:
+                parts = [x.strip() for x in line.strip().strip("|").split("|")]
+                vals[parts[0]] = float(parts[1])
+            elif ":" in line and not line.startswith(("#", "|", " ")):
+                k, v = line.split(":", 1)
+                try:
+                    vals[k.strip()] = float(v)
+                except ValueError:
+                    pass
+    if vals.get("hash") != source_hash():
+        return None
+    return vals
 
 
 def main():
@@ -81,10 +119,20 @@ def main():
         ms = sum(r.stats["levels"][dom]["join_ms"] for r in results) / len(results)
         nbytes = levels[dom]["algorithmic_bytes"]
         achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        prof = profiled_counters(dom, args.workload)
+        traffic = None
+        valu = None
+        if prof is not None:
+            traffic = prof.get("traffic_bytes_per_launch")
+            if prof.get("SQ_INSTS_VALU"):
+                rate = prof["SQ_INSTS_VALU"] / (ms / 1e3)
+                valu = {"wave_insts_per_s": round(rate, 1), "peak": VALU_PEAK_WAVE_INSTS,
+                        "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4)}
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                    "traffic": None, "kernel": f"k_join<{dom},domain>",
-                    "kernel_ms": round(ms, 3), "algorithmic_bytes": nbytes}
+                    "traffic": traffic, "kernel": f"k_join_tiles<{dom}> (domain pass)",
+                    "kernel_ms": round(ms, 3), "algorithmic_bytes": nbytes,
+                    "valu": valu}
 
     cpu = None
     exact = None
