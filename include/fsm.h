@@ -69,7 +69,7 @@ typedef struct {
 /* Mode bits for fsm_mine / fsm_options.mode. */
 enum {
     FSM_PLAIN = 0,    /* level-by-level exact join (Sections 3-4) */
-    FSM_BATCHED = 1,  /* reserved: persistent multi-graph scheduling */
+    FSM_BATCHED = 1,  /* many graphs in one pass (fsm_mine_batch) */
     FSM_LEARNED = 2,  /* reserved: learned cost model for sizing */
     FSM_SAMPLED = 4   /* subgraph sampling during joining (Section 5) */
 };
@@ -102,6 +102,9 @@ typedef struct {
                                    subgraph position */
     double kernel_ms;         /* device time of this level (all passes) */
     double join_ms;           /* device time of the join's domain pass */
+    int64_t domain_passes;    /* domain passes run: 1 + reruns after the
+                                 quick-pattern table overflowed */
+    int64_t qp_capacity;      /* quick-pattern table slots of the last pass */
 } fsm_level_stats;
 
 typedef struct {
@@ -112,6 +115,13 @@ typedef struct {
     int64_t filtered_edges;        /* undirected edges whose labelled edge is frequent */
     fsm_level_stats level[FSM_MAX_SIZE + 1];
     double total_ms;               /* wall time of the mining call */
+    int32_t batch_chunk;           /* batched calls: the union pass (chunk)
+                                      this graph was mined in; level counters
+                                      describe that whole chunk */
+    int32_t batch_chunks;          /* chunks of the call (1 for fsm_mine) */
+    int32_t batch_splits;          /* chunks split after a table or memory
+                                      overflow */
+    int32_t reserved0;
 } fsm_stats;
 
 /* Options of fsm_mine_ex.  Zero-initialise, then set fields. */
@@ -183,6 +193,47 @@ int fsm_mine(const fsm_graph *g, int64_t support, int32_t max_size,
  * sampled embeddings (a lower bound).  Errors as fsm_mine, plus FSM_EINVAL
  * for a sampling rate outside (0, 1]. */
 int fsm_mine_ex(const fsm_graph *g, const fsm_options *opt, fsm_result **out);
+
+/* Mine many graphs in one pass (batched mode): every level runs as one
+ * launch per kernel over the disjoint union of the graphs, whose work items
+ * are load-balanced together; patterns are keyed by graph, so each graph's
+ * result equals what fsm_mine would return for it.
+ *   graphs     count handles from fsm_build_graph (count 1..2048)
+ *   supports   count thresholds, supports[i] for graphs[i] (each >= 1)
+ *   max_size   2..6 (2..7 when count == 1)
+ *   mode       FSM_PLAIN or FSM_BATCHED (same meaning here)
+ *   outs       receives count result handles; the per-level counters of
+ *              every result describe the union pass it was mined in
+ * Graphs are mined in chunks of at most 65536 vertices (fsm_mine_batch_ex).
+ * Errors: as fsm_mine; FSM_EUNSUPPORTED for more than 2048 graphs or
+ * max_size 7 with several graphs.  On failure no handle is returned. */
+int fsm_mine_batch(const fsm_graph *const *graphs, int32_t count,
+                   const int64_t *supports, int32_t max_size, uint32_t mode,
+                   fsm_result **outs);
+
+/* Options of fsm_mine_batch_ex.  Zero-initialise, then set fields. */
+typedef struct {
+    int32_t max_size;           /* 2..6 (2..7 when count == 1) */
+    uint32_t mode;              /* FSM_PLAIN or FSM_BATCHED (same meaning) */
+    int64_t chunk_vertices;     /* >0: at most this many vertices in one
+                                   union pass (a larger single graph gets a
+                                   pass of its own); 0: 65536 */
+    int32_t disable_pruning;    /* as fsm_options */
+    int32_t reserved0;
+    int64_t hash_capacity_min;  /* as fsm_options (first chunk) */
+    int64_t pattern_capacity_min;
+} fsm_batch_options;
+
+/* fsm_mine_batch with options.  Graphs are ordered by their most populous
+ * label (so one chunk's domain bitmaps fit all its graphs) and packed into
+ * chunks of at most chunk_vertices vertices; each chunk is one union pass.
+ * A chunk whose tables or bitmaps exceed the limits or device memory is
+ * split in two and rerun (counted in batch_splits); the quick-pattern table
+ * of each level starts at the size the earlier chunks needed per vertex.
+ * Errors as fsm_mine_batch; FSM_EINVAL for chunk_vertices < 0. */
+int fsm_mine_batch_ex(const fsm_graph *const *graphs, int32_t count,
+                      const int64_t *supports, const fsm_batch_options *opt,
+                      fsm_result **outs);
 
 /* Number of frequent patterns in a result (-1 for NULL). */
 int64_t fsm_result_count(const fsm_result *r);

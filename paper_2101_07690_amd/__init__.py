@@ -48,7 +48,8 @@ class LevelStats(ctypes.Structure):
                 ("quick_patterns", ctypes.c_int64), ("patterns", ctypes.c_int64),
                 ("frequent", ctypes.c_int64), ("stored", ctypes.c_int64),
                 ("algorithmic_bytes", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
+                ("domain_passes", ctypes.c_int64), ("qp_capacity", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -57,7 +58,16 @@ class Stats(ctypes.Structure):
                 ("dropped_duplicates", ctypes.c_int64),
                 ("filtered_edges", ctypes.c_int64),
                 ("level", LevelStats * (MAX_SIZE + 1)),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("batch_chunk", ctypes.c_int32),
+                ("batch_chunks", ctypes.c_int32), ("batch_splits", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("max_size", ctypes.c_int32), ("mode", ctypes.c_uint32),
+                ("chunk_vertices", ctypes.c_int64), ("disable_pruning", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("hash_capacity_min", ctypes.c_int64),
+                ("pattern_capacity_min", ctypes.c_int64)]
 
 
 class Options(ctypes.Structure):
@@ -110,6 +120,12 @@ def lib():
     L.fsm_mine.restype = ctypes.c_int
     L.fsm_mine_ex.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(vp)]
     L.fsm_mine_ex.restype = ctypes.c_int
+    L.fsm_mine_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64p, ctypes.c_int32,
+                                 ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.fsm_mine_batch.restype = ctypes.c_int
+    L.fsm_mine_batch_ex.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64p,
+                                    ctypes.POINTER(BatchOptions), ctypes.POINTER(vp)]
+    L.fsm_mine_batch_ex.restype = ctypes.c_int
     L.fsm_result_count.argtypes = [vp]
     L.fsm_result_count.restype = ctypes.c_int64
     L.fsm_result_patterns.argtypes = [vp, i32p, i32p, ctypes.POINTER(Code), i64p]
@@ -256,7 +272,8 @@ def _stats_dict(st):
             "dropped_self_loops": st.dropped_self_loops,
             "dropped_duplicates": st.dropped_duplicates,
             "filtered_edges": st.filtered_edges, "levels": levels,
-            "total_ms": st.total_ms}
+            "total_ms": st.total_ms, "batch_chunk": st.batch_chunk,
+            "batch_chunks": st.batch_chunks, "batch_splits": st.batch_splits}
 
 
 def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
@@ -275,6 +292,29 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
     h = ctypes.c_void_p()
     _check(lib().fsm_mine_ex(graph.handle, ctypes.byref(o), ctypes.byref(h)))
     return Result(h)
+
+
+def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
+               chunk_vertices: int = 0, disable_pruning: bool = False,
+               hash_capacity_min: int = 0, pattern_capacity_min: int = 0):
+    """Mine several graphs in union passes of at most ``chunk_vertices``
+    vertices (0: the library default); one Result per graph."""
+    n = len(graphs)
+    if len(supports) != n:
+        raise ValueError("one support per graph")
+    hs = (ctypes.c_void_p * n)(*[g.handle for g in graphs])
+    sup = np.ascontiguousarray(supports, dtype=np.int64)
+    outs = (ctypes.c_void_p * n)()
+    o = BatchOptions()
+    o.max_size = int(max_size)
+    o.mode = int(mode)
+    o.chunk_vertices = int(chunk_vertices)
+    o.disable_pruning = 1 if disable_pruning else 0
+    o.hash_capacity_min = int(hash_capacity_min)
+    o.pattern_capacity_min = int(pattern_capacity_min)
+    _check(lib().fsm_mine_batch_ex(hs, n, sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   ctypes.byref(o), outs))
+    return [Result(ctypes.c_void_p(outs[i])) for i in range(n)]
 
 
 def dissect(ids, adj):

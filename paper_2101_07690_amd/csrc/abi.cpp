@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.h"
 #include "internal.h"
@@ -175,6 +176,47 @@ int fsm_mine(const fsm_graph* g, int64_t support, int32_t max_size, uint32_t mod
     o.mode = mode;
     o.sampling_rate = 1.0;
     return fsm_mine_ex(g, &o, out);
+}
+
+int fsm_mine_batch_ex(const fsm_graph* const* graphs, int32_t count, const int64_t* supports,
+                      const fsm_batch_options* opt, fsm_result** outs) {
+    if (outs && count > 0)
+        for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
+    std::vector<fsm_result*> rs;
+    int rc = guarded([&] {
+        if (!graphs || !supports || !outs || !opt)
+            fail(FSM_EINVAL, "fsm_mine_batch: NULL argument");
+        if (count < 1) fail(FSM_EINVAL, "fsm_mine_batch: count must be >= 1");
+        if (count > 2048) fail(FSM_EUNSUPPORTED, "fsm_mine_batch: at most 2048 graphs");
+        if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
+            fail(FSM_EINVAL, "fsm_mine_batch: max_size must be in [2, %d]", FSM_MAX_SIZE);
+        if (opt->mode & ~(uint32_t)FSM_BATCHED)
+            fail(FSM_EINVAL, "fsm_mine_batch: unsupported mode bits 0x%x", opt->mode);
+        if (opt->chunk_vertices < 0) fail(FSM_EINVAL, "fsm_mine_batch: chunk_vertices < 0");
+        for (int32_t i = 0; i < count; ++i) {
+            if (!graphs[i]) fail(FSM_EINVAL, "fsm_mine_batch: graph %d is NULL", i);
+            if (supports[i] < 1) fail(FSM_EINVAL, "fsm_mine_batch: support %d must be >= 1", i);
+        }
+        if (count > 1 && opt->max_size > 6)
+            fail(FSM_EUNSUPPORTED, "fsm_mine_batch: batches of several graphs support sizes up to 6");
+        for (int32_t i = 0; i < count; ++i) rs.push_back(new fsm_result());
+        mine_batch(graphs, count, supports, *opt, rs.data());
+    });
+    if (rc != FSM_OK) {
+        for (fsm_result* r : rs) delete r;
+        return rc;
+    }
+    for (int32_t i = 0; i < count; ++i) outs[i] = rs[(size_t)i];
+    return FSM_OK;
+}
+
+int fsm_mine_batch(const fsm_graph* const* graphs, int32_t count, const int64_t* supports,
+                   int32_t max_size, uint32_t mode, fsm_result** outs) {
+    fsm_batch_options o;
+    memset(&o, 0, sizeof(o));
+    o.max_size = max_size;
+    o.mode = mode;
+    return fsm_mine_batch_ex(graphs, count, supports, &o, outs);
 }
 
 int64_t fsm_result_count(const fsm_result* r) { return r ? (int64_t)r->size.size() : -1; }

@@ -126,7 +126,7 @@ FSM_HD bool dissection_is(int n, uint64_t ob, uint64_t A, uint32_t Tstar, uint32
 // bit, so smaller integer = smaller sequence.  The label sequence of the
 // minimum is the sorted labels, so only label-respecting orders are tried.
 struct Canon {
-    uint64_t code;    // (labels: 6 bits each, first vertex most significant) << 21 | sequence
+    uint64_t code;    // labels (6 bits each, first vertex most significant) << n(n-1)/2 | sequence
     uint32_t slots;   // 3 bits per ORIGINAL position: min canonical position of its orbit
     uint32_t orbits;  // 3 bits per CANONICAL position: min canonical position of its orbit
 };
@@ -199,7 +199,7 @@ __host__ __device__ inline __attribute__((noinline)) Canon canonicalize(int n, u
     Canon r;
     uint64_t labs = 0;
     for (int i = 0; i < n; ++i) labs = (labs << 6) | (uint64_t)lab_at(L, best[i]);
-    r.code = (labs << 21) | bestseq;
+    r.code = (labs << (n * (n - 1) / 2)) | bestseq;
     r.slots = 0;
     r.orbits = 0;
     for (int i = 0; i < n; ++i) {
@@ -207,6 +207,26 @@ __host__ __device__ inline __attribute__((noinline)) Canon canonicalize(int n, u
         r.slots |= (uint32_t)orb[i] << (3 * best[i]);
     }
     return r;
+}
+
+// Fields of a pattern-table key: canonical code in the low bits (labels then
+// pair-bit sequence), graph id of a batch from bit 52.  A size-n code takes
+// n(n-1)/2 + 6n bits: 51 at n = 6, 63 at n = 7, so only sizes <= 6 carry a
+// graph id (size 7 is mined one graph at a time).
+constexpr int CODE_GRAPH_SHIFT = 52;
+
+FSM_HD constexpr bool code_has_graph(int n) { return n * (n - 1) / 2 + 6 * n <= CODE_GRAPH_SHIFT; }
+
+FSM_HD int code_label(uint64_t code, int n, int i) {
+    return (int)((code >> (n * (n - 1) / 2 + 6 * (n - 1 - i))) & 63u);
+}
+
+FSM_HD uint32_t code_seq(uint64_t code, int n) {
+    return (uint32_t)(code & ((1ull << (n * (n - 1) / 2)) - 1));
+}
+
+FSM_HD int code_graph(uint64_t code, int n) {
+    return code_has_graph(n) ? (int)(code >> CODE_GRAPH_SHIFT) : 0;
 }
 
 }  // namespace fsm

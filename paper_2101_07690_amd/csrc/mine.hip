@@ -26,6 +26,7 @@
 // position), and the MNI support is the smallest orbit popcount.  The QP
 // value word then holds VALID | FREQ | 3-bit orbit slot per position.
 #include <algorithm>
+#include <deque>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -43,7 +44,7 @@ constexpr uint64_t FREQ = 1ull << 62;
 constexpr uint64_t REGION_MASK = (1ull << 41) - 1;
 constexpr int JOIN_CHUNK = 4;   // work items fetched per queue access
 
-enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, ERR_MISSING = 8, ERR_FILL = 16 };
+enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, ERR_MISSING = 8, ERR_FILL = 16, ERR_BATCH = 32 };
 enum { MODE_DOMAIN = 0, MODE_COUNT = 1, MODE_FILL = 2 };
 enum { PIECE_KC = 0, PIECE_KL = 1, PIECE_TR = 2 };   // k-centre wedge, k-leaf wedge, triangle
 
@@ -96,16 +97,28 @@ __device__ __forceinline__ int64_t wave_excl(int64_t v, int lane) {
     return inc - v;
 }
 
+// Inserting tables hold at most half their slots: past that load (or after
+// PROBE_LIMIT probes) an insert gives up and raises the overflow flag, and
+// the host reruns the pass with a larger table.  Lookups are never cut short.
+constexpr uint64_t PROBE_LIMIT = 4096;
+
+__device__ __forceinline__ bool over_load(const unsigned* count, uint64_t mask) {
+    const unsigned c = __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint64_t)c * 2 > mask;
+}
+
 // Find `key`; insert it when `insert` (CAS on an empty slot).  Returns the
-// slot, or -1 when absent (lookup) or the table is full (flag raised).
+// slot, or -1 when absent (lookup) or the insert gave up (flag raised).
 __device__ int64_t ht_probe(uint64_t* kv, uint64_t mask, uint64_t key, bool insert,
                             unsigned* count, uint32_t* flags, uint32_t bit) {
     uint64_t h = mix64(key) & mask;
-    for (uint64_t i = 0; i <= mask; ++i) {
+    const uint64_t limit = insert ? (mask < PROBE_LIMIT ? mask : PROBE_LIMIT) : mask;
+    for (uint64_t i = 0; i <= limit; ++i) {
         uint64_t cur = kv[2 * h];
         if (cur == key) return (int64_t)h;
         if (cur == EMPTY_KEY) {
             if (!insert) return -1;
+            if (over_load(count, mask)) break;
             unsigned long long prev =
                 atomicCAS((unsigned long long*)&kv[2 * h], (unsigned long long)EMPTY_KEY,
                           (unsigned long long)key);
@@ -126,10 +139,12 @@ __device__ int64_t ht_probe(uint64_t* kv, uint64_t mask, uint64_t key, bool inse
 // ordered subgraph (labels L, adjacency A) for the canonical pass.
 __device__ __forceinline__ int64_t qp_slot(const Rec& R, uint64_t key, uint64_t L, uint64_t A) {
     uint64_t h = mix64(key) & R.q.mask;
-    for (uint64_t i = 0; i <= R.q.mask; ++i) {
+    const uint64_t limit = R.q.mask < PROBE_LIMIT ? R.q.mask : PROBE_LIMIT;
+    for (uint64_t i = 0; i <= limit; ++i) {
         const uint64_t cur = R.q.kv[2 * h];
         if (cur == key) return (int64_t)h;
         if (cur == EMPTY_KEY) {
+            if (over_load(R.q.count, R.q.mask)) break;
             const unsigned long long prev =
                 atomicCAS((unsigned long long*)&R.q.kv[2 * h], (unsigned long long)EMPTY_KEY,
                           (unsigned long long)key);
@@ -224,12 +239,14 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
         p[i] = v;
 }
 
-// rank of each vertex among the vertices of its frequent label (any order)
-__global__ void k_label_rank(const int32_t* vf, int64_t n, unsigned* cnt, int32_t* rank) {
+// rank of each vertex among the vertices of its graph with its frequent
+// label (any order)
+__global__ void k_label_rank(const int32_t* vf, const int32_t* vg, int F, int64_t n,
+                             unsigned* cnt, int32_t* rank) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int l = vf[v];
-        rank[v] = l >= 0 ? (int32_t)atomicAdd(&cnt[l], 1u) : 0;
+        rank[v] = l >= 0 ? (int32_t)atomicAdd(&cnt[(size_t)vg[v] * F + l], 1u) : 0;
     }
 }
 
@@ -239,32 +256,35 @@ __global__ void k_vinfo(const int32_t* vf, const int32_t* rank, int64_t n, uint3
         vinfo[v] = vf[v] >= 0 ? ((uint32_t)vf[v] << 26 | (uint32_t)rank[v]) : 0xffffffffu;
 }
 
-__global__ void k_vertex_flabel(const int32_t* lab, int64_t n, const int32_t* fmap, int32_t* vf) {
+__global__ void k_vertex_flabel(const int32_t* lab, const int32_t* vg, int NL, int64_t n,
+                                const int32_t* fmap, int32_t* vf) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x)
-        vf[v] = fmap[lab[v]];
+        vf[v] = fmap[(size_t)vg[v] * NL + lab[v]];
 }
 
 // frequent-edge subgraph G_f: keep (v, w) when both labels are frequent and
 // the labelled edge is frequent
-__global__ void k_gf_count(const int32_t* row, const int32_t* col, const int32_t* vf, int64_t n,
-                           const uint8_t* freq2, int F, int64_t* cnt) {
+__global__ void k_gf_count(const int32_t* row, const int32_t* col, const int32_t* vf,
+                           const int32_t* vg, int64_t n, const uint8_t* freq2, int F,
+                           int64_t* cnt) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         int64_t c = 0;
         int a = vf[v];
+        const uint8_t* f2 = freq2 + (size_t)vg[v] * F * F;
         if (a >= 0)
             for (int32_t e = row[v]; e < row[v + 1]; ++e) {
                 int b = vf[col[e]];
-                if (b >= 0 && freq2[a * F + b]) ++c;
+                if (b >= 0 && f2[a * F + b]) ++c;
             }
         cnt[v] = c;
     }
 }
 
-__global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t* vf, int64_t n,
-                          const uint8_t* freq2, int F, const int64_t* off, int64_t total,
-                          int32_t* frow, int32_t* fcol) {
+__global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t* vf,
+                          const int32_t* vg, int64_t n, const uint8_t* freq2, int F,
+                          const int64_t* off, int64_t total, int32_t* frow, int32_t* fcol) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
          v += (int64_t)gridDim.x * blockDim.x) {
         if (v == n) { frow[n] = (int32_t)total; continue; }
@@ -272,10 +292,11 @@ __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t*
         frow[v] = (int32_t)o;
         int a = vf[v];
         if (a < 0) continue;
+        const uint8_t* f2 = freq2 + (size_t)vg[v] * F * F;
         for (int32_t e = row[v]; e < row[v + 1]; ++e) {
             int32_t w = col[e];
             int b = vf[w];
-            if (b >= 0 && freq2[a * F + b]) fcol[o++] = w;
+            if (b >= 0 && f2[a * F + b]) fcol[o++] = w;
         }
     }
 }
@@ -335,6 +356,7 @@ struct L2Args {
     const int32_t* row;
     const int32_t* col;
     const int32_t* vf;
+    const int32_t* vg;       // graph of each vertex (a batch is one disjoint union)
     int64_t n;
     Rec R;
     unsigned long long* emitted;
@@ -354,6 +376,7 @@ __global__ __launch_bounds__(TPB) void k_level2(L2Args a) {
     for (int64_t u = wave_id_global(); u < a.n; u += nwaves) {
         const int lu = a.vf[u];
         if (lu < 0) continue;
+        const uint64_t gid = (uint64_t)a.vg[u];
         const int32_t rb = a.row[u], re = a.row[u + 1];
         int64_t base = (MODE == MODE_FILL) ? a.offsets[u] : 0, total = 0;
         for (int32_t e0 = rb; e0 < re; e0 += 64) {
@@ -366,10 +389,10 @@ __global__ __launch_bounds__(TPB) void k_level2(L2Args a) {
             }
             int64_t s = -1;
             if (lw >= 0) {
-                uint64_t key = (uint64_t)lu << 6 | (uint64_t)lw;
+                uint64_t key = gid << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
                 if (MODE == MODE_DOMAIN) {
                     int32_t v[2] = {(int32_t)u, w};
-                    uint64_t L = (uint64_t)lu | (uint64_t)lw << 6;
+                    uint64_t L = (uint64_t)lu | (uint64_t)lw << 6 | gid << 48;
                     record<2>(a.R, key, L, add_edge(0, 0, 1), v);
                     ++emit;
                 } else {
@@ -405,6 +428,7 @@ struct L3Args {
     const int32_t* row;    // G_f
     const int32_t* col;
     const int32_t* vf;
+    const int32_t* vg;
     int64_t n;
     NbrHash nh;
     Rec R;
@@ -442,6 +466,7 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
             continue;
         }
         const int lc = a.vf[c];
+        const uint64_t gid = (uint64_t)a.vg[c];
         int64_t base = (MODE == MODE_FILL) ? a.offsets[c] : 0, total = 0;
         for (int64_t r0 = 0; r0 < npairs; r0 += 64) {
             const int64_t r = r0 + lane;
@@ -457,8 +482,8 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
                 lw = a.vf[w];
                 tri = c < u && has_edge(a.nh, u, w);
             }
-            const uint64_t L = (uint64_t)lc | (uint64_t)lu << 6 | (uint64_t)lw << 12;
-            const uint64_t kw = (uint64_t)lc << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
+            const uint64_t L = (uint64_t)lc | (uint64_t)lu << 6 | (uint64_t)lw << 12 | gid << 48;
+            const uint64_t kw = gid << 19 | (uint64_t)lc << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
             const uint64_t kt = (1ull << 18) | kw;
             const uint64_t Aw = add_edge(add_edge(0, 0, 1), 0, 2);
             const int32_t v[3] = {(int32_t)c, u, w};
@@ -514,7 +539,8 @@ struct JoinArgs {
     const int64_t* npieces;
     const int32_t* leafoff;
     NbrHash nh;
-    const uint8_t* f3;       // [2][F][F][F]: 0 wedge (centre first), 1 triangle
+    const int32_t* vg;
+    const uint8_t* f3;       // per graph [2][F][F][F]: 0 wedge (centre first), 1 triangle
     int F;
     const int32_t* par;      // parents, rows of (M vertices, QP slot)
     const uint64_t* padj;    // parent level: packed adjacency per QP slot
@@ -553,9 +579,9 @@ __device__ __forceinline__ uint64_t sample_hash(uint64_t seed, int n, int32_t k,
 // PHASE 0: domain pass (record) or count pass (count); PHASE 1: fill pass,
 // writing rows from `dst`.  Returns the number of children accepted.
 template <int N, int MODE, int PHASE>
-__device__ int children(const JoinArgs& a, const int32_t (&cv)[N], int i, uint32_t types,
-                       uint32_t ec, uint64_t PA, uint64_t L, uint64_t ob, int32_t pslot, int lu,
-                       int lw, int32_t* dst) {
+__device__ int children(const JoinArgs& a, const uint8_t* f3, const int32_t (&cv)[N], int i,
+                       uint32_t types, uint32_t ec, uint64_t PA, uint64_t L, uint64_t ob,
+                       int32_t pslot, int lu, int lw, int32_t* dst) {
     constexpr int M = N - 2;
     const uint32_t Tstar = (1u << i) | (1u << M) | (1u << (M + 1));
     const uint32_t kbit = 1u << i;
@@ -590,9 +616,9 @@ __device__ int children(const JoinArgs& a, const int32_t (&cv)[N], int i, uint32
                         const bool kb = (amask(A, i) >> j) & 1u;
                         const bool kc = (amask(A, i) >> c) & 1u;
                         const int lb = lab_at(L, j), lc = lab_at(L, c);
-                        if (kb && kc) ok = f3_at(a.f3, a.F, 1, lk, lb, lc);
-                        else if (kb) ok = f3_at(a.f3, a.F, 0, lb, lk, lc);
-                        else if (kc) ok = f3_at(a.f3, a.F, 0, lc, lk, lb);
+                        if (kb && kc) ok = f3_at(f3, a.F, 1, lk, lb, lc);
+                        else if (kb) ok = f3_at(f3, a.F, 0, lb, lk, lc);
+                        else if (kc) ok = f3_at(f3, a.F, 0, lc, lk, lb);
                     }
                 }
             }
@@ -654,6 +680,7 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                 L |= (uint64_t)a.vf[cv[j]] << (6 * j);
             }
             const int lk = a.vf[k];
+            const uint8_t* f3 = a.f3 + (size_t)a.vg[k] * 2 * a.F * a.F * a.F;
             const int32_t rk = a.row[k];
             const int32_t dk = a.row[k + 1] - rk;
             const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
@@ -699,13 +726,13 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                     if (ok) {
                         const int lu = a.vf[u], lw = a.vf[w];
                         if (centre) {
-                            if (f3_at(a.f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
-                            if (f3_at(a.f3, a.F, 1, lk, lu, lw)) {
+                            if (f3_at(f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
+                            if (f3_at(f3, a.F, 1, lk, lu, lw)) {
                                 bytes += 8;
                                 if (has_edge(a.nh, u, w)) types |= 1u << PIECE_TR;
                             }
                         } else {
-                            if (f3_at(a.f3, a.F, 0, lu, lk, lw)) types |= 1u << PIECE_KL;
+                            if (f3_at(f3, a.F, 0, lu, lk, lw)) types |= 1u << PIECE_KL;
                         }
                     }
                 }
@@ -726,8 +753,8 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                         if (has_edge(a.nh, cv[j], w)) ec |= 1u << (2 * j + 1);
                     }
                     ob = rank_bits<N>(cv);
-                    got = children<N, MODE, 0>(a, cv, i, types, ec, PA, Lc, ob, pslot, lu, lw,
-                                               nullptr);
+                    got = children<N, MODE, 0>(a, f3, cv, i, types, ec, PA, Lc, ob, pslot, lu,
+                                               lw, nullptr);
                     bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
                 }
                 if (MODE == MODE_DOMAIN) {
@@ -738,8 +765,8 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                         // same enumeration again, now writing at this lane's rows
                         const int64_t r2 = base + total + ex;
                         if (r2 + got <= a.out_rows)
-                            children<N, MODE, 1>(a, cv, i, types, ec, PA, Lc, ob, pslot, lu, lw,
-                                                 a.out + r2 * (N + 1));
+                            children<N, MODE, 1>(a, f3, cv, i, types, ec, PA, Lc, ob, pslot, lu,
+                                                 lw, a.out + r2 * (N + 1));
                         else
                             atomicOr(a.R.flags, ERR_FILL);
                     }
@@ -865,6 +892,7 @@ struct TileArgs {
     const int32_t* row;
     const int32_t* col;
     const uint32_t* vinfo;   // frequent label << 26 | rank within the label
+    const int32_t* vg;       // graph of each vertex
     const int64_t* npieces;
     const int32_t* leafoff;
     NbrHash nh;
@@ -885,6 +913,7 @@ struct TileArgs {
     uint32_t W;
     int prune;
     const Rec* rec;          // QP table (insert path)
+    const uint32_t* flags;   // overflow / error bits of the pass
     unsigned long long* ctr; // [emitted, candidates, -, bytes]
     int sampled;
     uint64_t seed;
@@ -952,7 +981,8 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
 // the connecting-edge subsets that the Section 4.5 pruning rejects are
 // excluded from the enumeration up front.
 template <int N>
-__device__ __forceinline__ int children_tile(const TileArgs& a, const int32_t (&cv)[N],
+__device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f3,
+                                             const int32_t (&cv)[N],
                                              const int32_t (&lr)[N], int i, uint32_t types,
                                              uint32_t ec, uint64_t PA, uint64_t L, int32_t pslot,
                                              int lu, int lw, LaneCache& c) {
@@ -996,8 +1026,8 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const int32_t (&
             const int j = b >> 1;
             const bool kb = (PA >> (8 * i + j)) & 1u;
             const int lb = lab_at(L, j), lc = (b & 1) ? lw : lu;
-            const bool ok2 = kb ? f3_at(a.f3, a.F, 1, lk, lb, lc) : f3_at(a.f3, a.F, 0, lc, lk, lb);
-            const bool okl = (b & 1) ? (kb ? f3_at(a.f3, a.F, 0, lb, lk, lc) : true) : ok2;
+            const bool ok2 = kb ? f3_at(f3, a.F, 1, lk, lb, lc) : f3_at(f3, a.F, 0, lc, lk, lb);
+            const bool okl = (b & 1) ? (kb ? f3_at(f3, a.F, 0, lb, lk, lc) : true) : ok2;
             if (!ok2) allow_both &= ~(1u << b);
             if (!okl) allow_kl &= ~(1u << b);
         }
@@ -1076,6 +1106,9 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
     LaneCache c{EMPTY_KEY, 0, EMPTY_KEY, 0, 0, 0};
     int64_t g = 0;
     for (int64_t t = wave_id_global(); t < a.ntiles; t += nw) {
+        // an overflowed pass is rerun with a larger table: stop early
+        if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & OVF_QP)
+            break;
         // group of tile t: last g with toff[g] <= t (t only grows: gallop)
         {
             int64_t step = 1;
@@ -1097,6 +1130,8 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
         const int32_t dk = a.row[k + 1] - rk;
         const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
         const int lk = (int)(a.vinfo[k] >> 26);
+        const uint64_t gid = (uint64_t)a.vg[k];
+        const uint8_t* f3 = a.f3 + (size_t)gid * 2 * a.F * a.F * a.F;
         // this lane's piece
         int32_t u = -1, w = -1, lru = 0, lrw = 0;
         uint32_t types = 0;
@@ -1128,12 +1163,12 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
                 lru = (int32_t)(iu & RANK_MASK);
                 lrw = (int32_t)(iw & RANK_MASK);
                 if (centre) {
-                    if (f3_at(a.f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
-                    if (f3_at(a.f3, a.F, 1, lk, lu, lw)) {
+                    if (f3_at(f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
+                    if (f3_at(f3, a.F, 1, lk, lu, lw)) {
                         bytes += 8;
                         if (has_edge(a.nh, u, w)) types |= 1u << PIECE_TR;
                     }
-                } else if (f3_at(a.f3, a.F, 0, lu, lk, lw)) {
+                } else if (f3_at(f3, a.F, 0, lu, lk, lw)) {
                     types |= 1u << PIECE_KL;
                 }
             }
@@ -1176,10 +1211,11 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             cv[M] = u;
             cv[M + 1] = w;
             const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
-            const uint64_t Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1));
+            const uint64_t Lc =
+                L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
             lr[M] = lru;
             lr[M + 1] = lrw;
-            const int got = children_tile<N>(a, cv, lr, i, types, ec, PA, Lc, pslot, lu, lw, c);
+            const int got = children_tile<N>(a, f3, cv, lr, i, types, ec, PA, Lc, pslot, lu, lw, c);
             emit += (unsigned long long)got;
             bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
         }
@@ -1233,8 +1269,15 @@ __global__ void k_qp_canon(CanonArgs a) {
     for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < a.slots;
          s += (uint64_t)gridDim.x * blockDim.x) {
         if (a.q.kv[2 * s] == EMPTY_KEY) continue;
-        const Canon cn = canonicalize(a.n, a.q.lab[s], a.q.adj[s]);
-        const int64_t p = ht_probe(a.c.kv, a.c.mask, cn.code, true, a.c.count, a.flags, OVF_CODE);
+        const uint64_t L = a.q.lab[s];
+        const uint64_t gid = L >> 48;
+        const Canon cn = canonicalize(a.n, L, a.q.adj[s]);
+        if (gid && !code_has_graph(a.n)) {
+            atomicOr(a.flags, ERR_BATCH);
+            continue;
+        }
+        const uint64_t code = cn.code | gid << CODE_GRAPH_SHIFT;
+        const int64_t p = ht_probe(a.c.kv, a.c.mask, code, true, a.c.count, a.flags, OVF_CODE);
         if (p < 0) continue;
         a.c.info[p] = VALID | cn.orbits;   // same value from every QP of the pattern
         a.q.pat[s] = (int32_t)p;
@@ -1318,17 +1361,124 @@ __global__ __launch_bounds__(TPB) void k_mni(MniArgs a) {
     }
 }
 
-// FREQ bit on every QP whose pattern reached the threshold
-__global__ void k_mark_frequent(QPTab q, uint64_t slots, const int64_t* sup, int64_t t) {
+// FREQ bit on every QP whose pattern reached its graph's threshold
+__global__ void k_mark_frequent(QPTab q, uint64_t slots, const uint64_t* ckv, const int64_t* sup,
+                                const int64_t* tg, int n) {
     for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
          s += (uint64_t)gridDim.x * blockDim.x) {
         if (q.kv[2 * s] == EMPTY_KEY) continue;
         uint64_t v = q.kv[2 * s + 1];
-        if ((v & VALID) && sup[q.pat[s]] >= t) q.kv[2 * s + 1] = v | FREQ;
+        if (!(v & VALID)) continue;
+        const int32_t p = q.pat[s];
+        if (sup[p] >= tg[code_graph(ckv[2 * p], n)]) q.kv[2 * s + 1] = v | FREQ;
     }
 }
 
 // ================================================================== host
+
+// One graph of a batch copied into the union CSR: vertex ids shifted by
+// voff, CSR offsets by eoff, labels mapped to the batch's label ids.
+__global__ void k_union_graph(const int32_t* row, const int32_t* col, const int32_t* lab,
+                              int64_t n, int64_t nnz, int64_t voff, int64_t eoff,
+                              const int32_t* lmap, int32_t gid, int32_t* urow, int32_t* ucol,
+                              int32_t* ulab, int32_t* uvg) {
+    const int64_t items = n > nnz ? n : nnz;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < items;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        if (x < n) {
+            urow[voff + x] = (int32_t)(row[x] + eoff);
+            ulab[voff + x] = lmap[lab[x]];
+            uvg[voff + x] = gid;
+        }
+        if (x < nnz) ucol[eoff + x] = (int32_t)(col[x] + voff);
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// The graph a mining call works on: one built graph, or the disjoint union
+// of a batch (every connected pattern lies in one graph, so keying patterns
+// by graph id keeps the graphs' results apart).
+struct GraphView {
+    int64_t n = 0, nnz = 0;
+    const int32_t* row = nullptr;
+    const int32_t* col = nullptr;
+    const int32_t* lab = nullptr;       // label id 0..L-1
+    const int32_t* vg = nullptr;        // graph id per vertex
+    DBuf<int32_t> urow, ucol, ulab, uvg;
+    int32_t ngraphs = 1, L = 0;
+    std::vector<int32_t> label_value;   // label id -> caller's label
+    std::vector<int64_t> count;         // [graph * L + label] vertices
+
+    void single(const fsm_graph* g) {
+        n = g->n;
+        nnz = g->nnz;
+        row = g->row.p;
+        col = g->col.p;
+        lab = g->lab.p;
+        ngraphs = 1;
+        L = g->num_labels;
+        label_value = g->label_value;
+        count = g->label_count;
+        uvg.alloc((size_t)n);
+        uvg.zero();
+        vg = uvg.p;
+    }
+
+    void batch(const fsm_graph* const* gs, int32_t k) {
+        ngraphs = k;
+        std::vector<int32_t> vals;
+        for (int32_t i = 0; i < k; ++i) {
+            n += gs[i]->n;
+            nnz += gs[i]->nnz;
+            vals.insert(vals.end(), gs[i]->label_value.begin(), gs[i]->label_value.end());
+        }
+        if (n > INT32_MAX || nnz > INT32_MAX)
+            fail(FSM_EUNSUPPORTED, "batch exceeds 2^31-1 vertices or CSR entries");
+        std::sort(vals.begin(), vals.end());
+        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        label_value = vals;
+        L = (int32_t)vals.size();
+        count.assign((size_t)k * L, 0);
+        urow.alloc((size_t)n + 1);
+        ucol.alloc((size_t)(nnz > 0 ? nnz : 1));
+        ulab.alloc((size_t)n);
+        uvg.alloc((size_t)n);
+        int64_t voff = 0, eoff = 0;
+        hipStream_t st = stream();
+        std::vector<DBuf<int32_t>> maps;
+        for (int32_t i = 0; i < k; ++i) {
+            const fsm_graph* g = gs[i];
+            std::vector<int32_t> lm((size_t)g->num_labels);
+            for (int32_t r = 0; r < g->num_labels; ++r) {
+                lm[(size_t)r] = (int32_t)(std::lower_bound(vals.begin(), vals.end(),
+                                                           g->label_value[(size_t)r]) -
+                                          vals.begin());
+                count[(size_t)i * L + lm[(size_t)r]] = g->label_count[(size_t)r];
+            }
+            maps.emplace_back(lm.size());
+            to_device(maps.back().p, lm.data(), lm.size());
+            const int64_t items = std::max(g->n, g->nnz);
+            k_union_graph<<<grid_for(items, 256), 256, 0, st>>>(
+                g->row.p, g->col.p, g->lab.p, g->n, g->nnz, voff, eoff, maps.back().p, i, urow.p,
+                ucol.p, ulab.p, uvg.p);
+            FSM_LAUNCH_CHECK();
+            voff += g->n;
+            eoff += g->nnz;
+        }
+        k_fill_i32<<<1, 1, 0, st>>>(urow.p + n, 1, (int32_t)nnz);
+        FSM_LAUNCH_CHECK();
+        FSM_HIP(hipStreamSynchronize(st));
+        row = urow.p;
+        col = ucol.p;
+        lab = ulab.p;
+        vg = uvg.p;
+    }
+};
 
 struct Tables {
     DBuf<uint64_t> qkv, qadj, qlab, ckv, cinfo;
@@ -1389,9 +1539,12 @@ uint64_t pow2_at_least(uint64_t x) {
 }
 
 struct Miner {
-    const fsm_graph* g;
+    GraphView gv;
+    const GraphView* g = &gv;
     fsm_options opt;
     hipStream_t st;
+    std::vector<int64_t> tg;              // support threshold of each graph
+    DBuf<int64_t> dtg;
     int F = 0;
     std::vector<int32_t> fvalue;          // frequent id -> caller label
     DBuf<int32_t> vf;                     // frequent id per vertex or -1
@@ -1414,7 +1567,9 @@ struct Miner {
     uint32_t W = 1;
     unsigned grid_persistent = 1024;
     Level lv[FSM_MAX_SIZE + 1];
-    fsm_result* res;
+    std::vector<fsm_result*> res;         // one per graph
+
+    uint64_t qhint[FSM_MAX_SIZE + 1] = {};   // first QP table size per level (0: default)
 
     uint64_t qcap0() const {
         uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 14);
@@ -1437,8 +1592,10 @@ struct Miner {
     // fills L.freq and the FREQ bits of the QP table.
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
-        uint64_t qcap = L.tab.qcap ? L.tab.qcap : qcap0();
+        uint64_t qcap = L.tab.qcap ? L.tab.qcap : std::max(qcap0(), qhint[L.n]);
         for (int attempt = 0;; ++attempt) {
+            L.st.domain_passes = attempt + 1;
+            L.st.qp_capacity = (int64_t)qcap;
             // child keys carry the parent's QP slot in 29 bits
             if (qcap > (1ull << 29))
                 fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
@@ -1481,7 +1638,10 @@ struct Miner {
                          flags.p, L.n, L.tab.qcap};
             k_qp_canon<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(ca);
             FSM_LAUNCH_CHECK();
-            if (!(scalar_to_host(flags.p) & OVF_CODE)) break;
+            const uint32_t cf = scalar_to_host(flags.p);
+            if (cf & ERR_BATCH)
+                fail(FSM_EUNSUPPORTED, "batches of several graphs support sizes up to 6");
+            if (!(cf & OVF_CODE)) break;
             if (attempt >= 4) fail(FSM_EOVERFLOW, "pattern table overflow at size %d", L.n);
             ccap *= 4;
         }
@@ -1506,9 +1666,8 @@ struct Miner {
                   {ppool.p, lrank.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
         k_mni<<<grid_for((int64_t)L.tab.ccap, 1, 1u << 16), TPB, 0, st>>>(m);
         FSM_LAUNCH_CHECK();
-        k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(q, L.tab.qcap,
-                                                                             L.tab.csup.p,
-                                                                             opt.support);
+        k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(
+            q, L.tab.qcap, L.tab.ckv.p, L.tab.csup.p, dtg.p, L.n);
         FSM_LAUNCH_CHECK();
         std::vector<uint64_t> hk;
         std::vector<int64_t> hs;
@@ -1516,7 +1675,7 @@ struct Miner {
         to_host(hs, osup.p, npat);
         L.freq.clear();
         for (unsigned i = 0; i < npat; ++i)
-            if (hs[i] >= opt.support) L.freq.emplace_back(hk[i], hs[i]);
+            if (hs[i] >= tg[(size_t)code_graph(hk[i], L.n)]) L.freq.emplace_back(hk[i], hs[i]);
         std::sort(L.freq.begin(), L.freq.end());
         L.st.frequent = (int64_t)L.freq.size();
     }
@@ -1559,7 +1718,7 @@ void Miner::level2() {
     Level& L = lv[2];
     L.n = 2;
     auto launch = [&](Rec R) {
-        L2Args a{g->row.p, g->col.p, vf.p, g->n, R, counters.p, nullptr, nullptr, nullptr, 0};
+        L2Args a{g->row, g->col, vf.p, g->vg, g->n, R, counters.p, nullptr, nullptr, nullptr, 0};
         k_level2<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
         FSM_LAUNCH_CHECK();
     };
@@ -1567,23 +1726,24 @@ void Miner::level2() {
 }
 
 void Miner::build_gf() {
-    // frequent labelled edges from the size-2 results
-    std::vector<uint8_t> f2((size_t)F * F, 0);
+    // frequent labelled edges of every graph from the size-2 results
+    std::vector<uint8_t> f2((size_t)g->ngraphs * F * F, 0);
     for (auto& kv : lv[2].freq) {
-        int a = (int)((kv.first >> (21 + 6)) & 63), b = (int)((kv.first >> 21) & 63);
-        f2[(size_t)a * F + b] = f2[(size_t)b * F + a] = 1;
+        const int a = code_label(kv.first, 2, 0), b = code_label(kv.first, 2, 1);
+        uint8_t* t = f2.data() + (size_t)code_graph(kv.first, 2) * F * F;
+        t[(size_t)a * F + b] = t[(size_t)b * F + a] = 1;
     }
     DBuf<uint8_t> df2(f2.size());
     to_device(df2.p, f2.data(), f2.size());
     const int64_t n = g->n;
     DBuf<int64_t> cnt((size_t)n + 1);
-    k_gf_count<<<grid_for(n, TPB), TPB, 0, st>>>(g->row.p, g->col.p, vf.p, n, df2.p, F, cnt.p);
+    k_gf_count<<<grid_for(n, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F, cnt.p);
     FSM_LAUNCH_CHECK();
     fnnz = scan_exclusive(cnt.p, cnt.p, n);
     frow.alloc((size_t)n + 1);
     fcol.alloc((size_t)(fnnz > 0 ? fnnz : 1));
-    k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row.p, g->col.p, vf.p, n, df2.p, F, cnt.p,
-                                                     fnnz, frow.p, fcol.p);
+    k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F,
+                                                     cnt.p, fnnz, frow.p, fcol.p);
     FSM_LAUNCH_CHECK();
     // per-vertex neighbour hash tables (load <= 1/2) and piece counts
     {
@@ -1604,14 +1764,14 @@ void Miner::build_gf() {
     leafoff.alloc((size_t)(fnnz > 0 ? fnnz : 1));
     k_pieces<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, npieces.p, leafoff.p);
     FSM_LAUNCH_CHECK();
-    res->stats.filtered_edges = fnnz / 2;
+    for (fsm_result* r : res) r->stats.filtered_edges = fnnz / 2;
 }
 
 void Miner::level3() {
     Level& L = lv[3];
     L.n = 3;
     auto launch = [&](Rec R) {
-        L3Args a{frow.p, fcol.p, vf.p, g->n, nh(), R, counters.p,
+        L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), R, counters.p,
                  nullptr, nullptr, nullptr, 0};
         k_level3<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
         FSM_LAUNCH_CHECK();
@@ -1619,11 +1779,11 @@ void Miner::level3() {
     domain_level(L, launch);
     // rooted frequent size-3 table for the joins and the pruning
     const size_t FF = (size_t)F * F * F;
-    std::vector<uint8_t> t(2 * FF, 0);
+    std::vector<uint8_t> t2(2 * FF * (size_t)g->ngraphs, 0);
     for (auto& kv : L.freq) {
         const uint64_t code = kv.first;
-        int l0 = (int)((code >> (21 + 12)) & 63), l1 = (int)((code >> (21 + 6)) & 63),
-            l2 = (int)((code >> 21) & 63);
+        uint8_t* t = t2.data() + 2 * FF * (size_t)code_graph(code, 3);
+        int l0 = code_label(code, 3, 0), l1 = code_label(code, 3, 1), l2 = code_label(code, 3, 2);
         const uint32_t seq = (uint32_t)(code & 7u);   // bits: (0,1) (0,2) (1,2)
         int ls[3] = {l0, l1, l2};
         if (seq == 7u) {
@@ -1637,8 +1797,8 @@ void Miner::level3() {
             t[((size_t)ls[c] * F + ls[y]) * F + ls[x]] = 1;
         }
     }
-    f3.alloc(t.size());
-    to_device(f3.p, t.data(), t.size());
+    f3.alloc(t2.size());
+    to_device(f3.p, t2.data(), t2.size());
 }
 
 // Group the work items (p, i) of a join by (p[i], parent QP, i) and count
@@ -1726,6 +1886,7 @@ void Miner::join(int n) {
         a.row = frow.p; a.col = fcol.p; a.vf = vf.p;
         a.npieces = npieces.p; a.leafoff = leafoff.p;
         a.nh = nh();
+        a.vg = g->vg;
         a.f3 = f3.p; a.F = F;
         a.par = P.emb.p; a.padj = P.tab.qadj.p;
         a.R = R;
@@ -1763,7 +1924,7 @@ void Miner::join(int n) {
         hrec = R;
         FSM_HIP(hipMemcpyAsync(drec.p, &hrec, sizeof(Rec), hipMemcpyHostToDevice, st));
         TileArgs t;
-        t.row = frow.p; t.col = fcol.p; t.vinfo = vinfo.p;
+        t.row = frow.p; t.col = fcol.p; t.vinfo = vinfo.p; t.vg = g->vg;
         t.npieces = npieces.p; t.leafoff = leafoff.p;
         t.nh = nh();
         t.f3 = f3.p; t.F = F;
@@ -1772,7 +1933,7 @@ void Miner::join(int n) {
         t.goff = G.goff.p; t.gcnt = G.gcnt.p; t.toff = G.toff.p;
         t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p;
         t.tile_p = G.tile_p;
-        t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p;
+        t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p; t.flags = R.flags;
         t.ctr = counters.p;
         t.prune = opt.disable_pruning ? 0 : 1;
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
@@ -1826,16 +1987,14 @@ void Miner::emit_results() {
             memset(&c, 0, sizeof(c));
             c.n = n;
             for (int i = 0; i < FSM_MAX_SIZE; ++i) c.label[i] = -1;
-            for (int i = 0; i < n; ++i) {
-                int fl = (int)((kv.first >> (21 + 6 * (n - 1 - i))) & 63);
-                c.label[i] = fvalue[(size_t)fl];
-            }
-            uint32_t seq = (uint32_t)(kv.first & ((1u << 21) - 1));
+            for (int i = 0; i < n; ++i) c.label[i] = fvalue[(size_t)code_label(kv.first, n, i)];
+            const uint32_t seq = code_seq(kv.first, n);
             for (int k = 0; k < npairs; ++k)
                 if ((seq >> (npairs - 1 - k)) & 1u) c.adj |= 1u << k;
-            res->size.push_back(n);
-            res->code.push_back(c);
-            res->support.push_back(kv.second);
+            fsm_result* r = res[(size_t)code_graph(kv.first, n)];
+            r->size.push_back(n);
+            r->code.push_back(c);
+            r->support.push_back(kv.second);
         }
     }
 }
@@ -1843,25 +2002,33 @@ void Miner::emit_results() {
 void Miner::run() {
     auto t0 = std::chrono::steady_clock::now();
     st = stream();
-    res->stats.max_size = opt.max_size;
-    res->stats.dropped_self_loops = g->dropped_loops;
-    res->stats.dropped_duplicates = g->dropped_dups;
-    // frequent labels: a pattern vertex of label l has at most count(l) images
-    std::vector<int32_t> fmap((size_t)g->num_labels, -1);
-    for (int32_t l = 0; l < g->num_labels; ++l)
-        if (g->label_count[(size_t)l] >= opt.support) {
-            if (F >= FSM_MAX_FREQ_LABELS)
-                fail(FSM_EUNSUPPORTED, "more than %d labels occur on >= %lld vertices",
-                     FSM_MAX_FREQ_LABELS, (long long)opt.support);
-            fmap[(size_t)l] = F++;
-            fvalue.push_back(g->label_value[(size_t)l]);
-        }
-    res->stats.frequent_labels = F;
+    for (fsm_result* r : res) r->stats.max_size = opt.max_size;
+    const int32_t G = g->ngraphs, NL = g->L;
+    // frequent labels: a pattern vertex of label l has at most count(l)
+    // images, so (graph, label) is kept when its graph's threshold allows
+    std::vector<int32_t> lid((size_t)NL, -1);       // label -> frequent id
+    std::vector<int32_t> fmap((size_t)G * NL, -1);  // (graph, label) -> frequent id or -1
+    for (int32_t gi = 0; gi < G; ++gi)
+        for (int32_t l = 0; l < NL; ++l)
+            if (g->count[(size_t)gi * NL + l] >= tg[(size_t)gi]) {
+                if (lid[(size_t)l] < 0) {
+                    if (F >= FSM_MAX_FREQ_LABELS)
+                        fail(FSM_EUNSUPPORTED, "more than %d labels reach the support threshold",
+                             FSM_MAX_FREQ_LABELS);
+                    lid[(size_t)l] = F++;
+                    fvalue.push_back(g->label_value[(size_t)l]);
+                }
+                fmap[(size_t)gi * NL + l] = lid[(size_t)l];
+            }
+    for (fsm_result* r : res) r->stats.frequent_labels = F;
     if (F == 0 || g->nnz == 0) {
-        res->stats.total_ms =
+        const double ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (fsm_result* r : res) r->stats.total_ms = ms;
         return;
     }
+    dtg.alloc(tg.size());
+    to_device(dtg.p, tg.data(), tg.size());
     int dev = 0;
     FSM_HIP(hipGetDevice(&dev));
     int cus = 0;
@@ -1870,19 +2037,19 @@ void Miner::run() {
     DBuf<int32_t> dmap(fmap.size());
     to_device(dmap.p, fmap.data(), fmap.size());
     vf.alloc((size_t)g->n);
-    k_vertex_flabel<<<grid_for(g->n, TPB), TPB, 0, st>>>(g->lab.p, g->n, dmap.p, vf.p);
+    k_vertex_flabel<<<grid_for(g->n, TPB), TPB, 0, st>>>(g->lab, g->vg, NL, g->n, dmap.p, vf.p);
     FSM_LAUNCH_CHECK();
-    // bitmaps are indexed by rank within a label: as many bits as the most
-    // common frequent label has vertices
+    // bitmaps are indexed by rank within (graph, label): as many bits as the
+    // most populous frequent (graph, label) has vertices
     int64_t maxcount = 1;
-    for (int32_t l = 0; l < g->num_labels; ++l)
-        if (fmap[(size_t)l] >= 0) maxcount = std::max(maxcount, g->label_count[(size_t)l]);
+    for (size_t x = 0; x < fmap.size(); ++x)
+        if (fmap[x] >= 0) maxcount = std::max(maxcount, g->count[x]);
     W = (uint32_t)((maxcount + 31) / 32);
     lrank.alloc((size_t)g->n);
     {
-        DBuf<unsigned> lcnt((size_t)F);
+        DBuf<unsigned> lcnt((size_t)G * F);
         lcnt.zero();
-        k_label_rank<<<grid_for(g->n, TPB), TPB, 0, st>>>(vf.p, g->n, lcnt.p, lrank.p);
+        k_label_rank<<<grid_for(g->n, TPB), TPB, 0, st>>>(vf.p, g->vg, F, g->n, lcnt.p, lrank.p);
         FSM_LAUNCH_CHECK();
     }
     if (maxcount > (int64_t)RANK_MASK)
@@ -1915,7 +2082,8 @@ void Miner::run() {
             Level& L = lv[2];
             materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
                                      int32_t* out, int64_t rows) {
-                L2Args a{frow.p, fcol.p, vf.p, g->n, rec(L), counters.p, counts, offsets, out, rows};
+                L2Args a{frow.p, fcol.p, vf.p, g->vg, g->n, rec(L), counters.p, counts, offsets,
+                         out, rows};
                 if (mode == MODE_COUNT) k_level2<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
                 else k_level2<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
                 FSM_LAUNCH_CHECK();
@@ -1925,7 +2093,7 @@ void Miner::run() {
             Level& L = lv[3];
             materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
                                      int32_t* out, int64_t rows) {
-                L3Args a{frow.p, fcol.p, vf.p, g->n, nh(), rec(L), counters.p,
+                L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), rec(L), counters.p,
                          counts, offsets, out, rows};
                 if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
                 else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
@@ -1949,20 +2117,114 @@ void Miner::run() {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (int n = 2; n <= opt.max_size; ++n) res->stats.level[n] = lv[n].st;
+    for (fsm_result* r : res)
+        for (int n = 2; n <= opt.max_size; ++n) r->stats.level[n] = lv[n].st;
     emit_results();
-    res->stats.total_ms =
+    const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (fsm_result* r : res) r->stats.total_ms = ms;
 }
 
 }  // namespace
 
 void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r) {
     Miner m;
-    m.g = g;
+    m.gv.single(g);
     m.opt = opt;
-    m.res = r;
+    m.tg.assign(1, opt.support);
+    m.res.assign(1, r);
+    r->stats.dropped_self_loops = g->dropped_loops;
+    r->stats.dropped_duplicates = g->dropped_dups;
+    r->stats.batch_chunks = 1;
     m.run();
+}
+
+// Most populous label of a graph: its bitmaps need ceil(that / 32) words.
+int64_t widest_label(const fsm_graph* g) {
+    int64_t m = 0;
+    for (int64_t c : g->label_count) m = std::max(m, c);
+    return m;
+}
+
+void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
+                const fsm_batch_options& bo, fsm_result* const* rs) {
+    const int64_t budget = bo.chunk_vertices > 0 ? bo.chunk_vertices : (int64_t)1 << 16;
+    // order by bitmap width (widest first), then pack consecutive graphs
+    std::vector<int32_t> ord((size_t)count);
+    for (int32_t i = 0; i < count; ++i) ord[(size_t)i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        return widest_label(gs[a]) > widest_label(gs[b]);
+    });
+    std::deque<std::vector<int32_t>> todo;
+    std::vector<int32_t> cur;
+    int64_t acc = 0;
+    for (int32_t i : ord) {
+        if (!cur.empty() && acc + gs[i]->n > budget) {
+            todo.push_back(std::move(cur));
+            cur.clear();
+            acc = 0;
+        }
+        cur.push_back(i);
+        acc += gs[i]->n;
+    }
+    todo.push_back(std::move(cur));
+
+    fsm_options o;
+    memset(&o, 0, sizeof(o));
+    o.max_size = bo.max_size;
+    o.mode = FSM_PLAIN;
+    o.disable_pruning = bo.disable_pruning;
+    o.sampling_rate = 1.0;
+    o.hash_capacity_min = bo.hash_capacity_min;
+    o.pattern_capacity_min = bo.pattern_capacity_min;
+    // quick patterns per union vertex seen so far, per level: the next
+    // chunk's tables start at that density (load <= 1/2, 25% slack)
+    double qpv[FSM_MAX_SIZE + 1] = {};
+    int32_t chunk = 0, splits = 0;
+    std::vector<int32_t> chunk_of((size_t)count, 0);
+    while (!todo.empty()) {
+        std::vector<int32_t> part = std::move(todo.front());
+        todo.pop_front();
+        std::vector<const fsm_graph*> pg;
+        std::vector<fsm_result*> pr;
+        int64_t nv = 0;
+        for (int32_t i : part) {
+            pg.push_back(gs[i]);
+            pr.push_back(rs[i]);
+            nv += gs[i]->n;
+        }
+        Miner m;
+        m.opt = o;
+        for (int n = 2; n <= FSM_MAX_SIZE; ++n)
+            if (qpv[n] > 0) m.qhint[n] = pow2_at_least((uint64_t)(2.5 * qpv[n] * (double)nv) + 16);
+        try {
+            m.gv.batch(pg.data(), (int32_t)pg.size());
+            for (int32_t i : part) m.tg.push_back(supports[i]);
+            m.res = pr;
+            m.run();
+        } catch (const Failure& f) {
+            if ((f.code != FSM_EOVERFLOW && f.code != FSM_ENOMEM) || part.size() < 2) throw;
+            (void)hipGetLastError();
+            FSM_HIP(hipStreamSynchronize(stream()));
+            for (fsm_result* r : pr) *r = fsm_result();
+            const size_t h = part.size() / 2;
+            todo.push_front(std::vector<int32_t>(part.begin() + (long)h, part.end()));
+            todo.push_front(std::vector<int32_t>(part.begin(), part.begin() + (long)h));
+            ++splits;
+            continue;
+        }
+        for (int n = 2; n <= o.max_size; ++n)
+            qpv[n] = std::max(qpv[n], (double)m.lv[n].st.quick_patterns / (double)std::max<int64_t>(nv, 1));
+        for (int32_t i : part) chunk_of[(size_t)i] = chunk;
+        ++chunk;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        rs[i]->stats.dropped_self_loops = gs[i]->dropped_loops;
+        rs[i]->stats.dropped_duplicates = gs[i]->dropped_dups;
+        rs[i]->stats.batch_chunk = chunk_of[(size_t)i];
+        rs[i]->stats.batch_chunks = chunk;
+        rs[i]->stats.batch_splits = splits;
+    }
 }
 
 }  // namespace fsm

@@ -165,3 +165,59 @@ def test_dissection_paper_example():
 def test_dissection_rejects_disconnected():
     with pytest.raises(fsm.FsmError):
         fsm.dissect([0, 1, 2, 3], adj_bits(4, [(0, 1), (2, 3)]))
+
+
+def test_mine_batch_rejects_bad_arguments():
+    import ctypes
+    L = fsm.lib()
+    outs = (ctypes.c_void_p * 2)()
+    sup = (ctypes.c_int64 * 2)(1, 1)
+    assert L.fsm_mine_batch(None, 2, sup, 4, 0, outs) == -1
+    hs = (ctypes.c_void_p * 2)(None, None)
+    assert L.fsm_mine_batch(hs, 0, sup, 4, 0, outs) == -1
+    assert L.fsm_mine_batch(hs, 2, sup, 4, 0, outs) == -1          # NULL graph handles
+    assert outs[0] is None and outs[1] is None
+
+
+def test_ctypes_structs_match_header(tmp_path):
+    # sizes and field offsets of the binding's structs, as the C compiler
+    # lays out the header
+    import ctypes
+    import subprocess
+    structs = {"fsm_code": fsm.Code, "fsm_level_stats": fsm.LevelStats,
+               "fsm_stats": fsm.Stats, "fsm_options": fsm.Options,
+               "fsm_batch_options": fsm.BatchOptions}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fsm.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.split() for line in subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_mine_batch_ex_rejects_bad_options():
+    import ctypes
+    L = fsm.lib()
+    outs = (ctypes.c_void_p * 1)()
+    sup = (ctypes.c_int64 * 1)(1)
+    hs = (ctypes.c_void_p * 1)(None)
+    o = fsm.BatchOptions()
+    o.max_size, o.chunk_vertices = 4, -1
+    assert L.fsm_mine_batch_ex(hs, 1, sup, ctypes.byref(o), outs) == -1
+    assert b"chunk_vertices" in L.fsm_last_error()
+    o.chunk_vertices, o.mode = 0, fsm.FSM_SAMPLED
+    assert L.fsm_mine_batch_ex(hs, 1, sup, ctypes.byref(o), outs) == -1
+    assert b"mode" in L.fsm_last_error()
+    assert L.fsm_mine_batch_ex(hs, 1, sup, None, outs) == -1
+    assert outs[0] is None

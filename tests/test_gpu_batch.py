@@ -1,0 +1,82 @@
+"""GPU parity of batched mining (many graphs in one pass): each graph's
+result must equal the oracle's, and equal what the plain per-graph call
+returns."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2101_07690_amd as fsm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def build(src, dst, lab):
+    return fsm.Graph(len(lab), src, dst, lab)
+
+
+def test_batch_of_tiny_graphs_matches_oracle():
+    cases = [synth.tiny_graph(8000 + s, 9, 14, 1 + s % 3) for s in range(24)]
+    sups = [1 + s % 3 for s in range(24)]
+    gs = [build(*c) for c in cases]
+    try:
+        for smax in (4, 5, 6):
+            print(f"tiny batch smax={smax}", flush=True)
+            res = fsm.mine_batch(gs, sups, smax)
+            for (s, d, lab), t, r in zip(cases, sups, res):
+                assert r.patterns == oracle.mine(len(lab), s, d, lab, t, smax)
+    finally:
+        for g in gs:
+            g.close()
+
+
+def test_batch_workload_graphs_match_oracle():
+    # graphs of the 256-graph batch workload that the oracle finishes quickly
+    ws = synth.batch_workload()
+    pick = [3, 5, 6, 8, 9]
+    gs = [build(ws[i]["src"], ws[i]["dst"], ws[i]["vertex_labels"]) for i in pick]
+    try:
+        res = fsm.mine_batch(gs, [ws[i]["support"] for i in pick], 5)
+        for i, r in zip(pick, res):
+            w = ws[i]
+            print(f"batch graph {i} n={w['n']}", flush=True)
+            assert r.patterns == oracle.mine(w["n"], w["src"], w["dst"], w["vertex_labels"],
+                                             w["support"], 5)
+    finally:
+        for g in gs:
+            g.close()
+
+
+def test_full_batch_equals_plain_calls():
+    ws = synth.batch_workload()
+    gs = [build(w["src"], w["dst"], w["vertex_labels"]) for w in ws]
+    try:
+        print("full batch", flush=True)
+        res = fsm.mine_batch(gs, [w["support"] for w in ws], 5)
+        assert len(res) == len(ws)
+        for i in range(0, len(ws), 8):
+            plain = fsm.mine(gs[i], ws[i]["support"], 5)
+            assert res[i].patterns == plain.patterns, i
+    finally:
+        for g in gs:
+            g.close()
+
+
+def test_single_graph_batch_equals_mine():
+    w = synth.workload("er3300")
+    with build(w["src"], w["dst"], w["vertex_labels"]) as g:
+        a = fsm.mine_batch([g], [10], 7)[0]
+        b = fsm.mine(g, 10, 7)
+    assert a.patterns == b.patterns
+
+
+def test_batch_rejects_size7_for_several_graphs():
+    s, d, lab = synth.tiny_graph(1, 6, 8, 1)
+    g1, g2 = build(s, d, lab), build(s, d, lab)
+    try:
+        with pytest.raises(fsm.FsmError) as e:
+            fsm.mine_batch([g1, g2], [1, 1], 7)
+        assert e.value.code == -5
+    finally:
+        g1.close()
+        g2.close()

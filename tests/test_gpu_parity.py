@@ -48,6 +48,36 @@ def test_tiny_random_graphs(seed):
             assert_same(got, oracle.mine(n, s, d, lab, t, smax))
 
 
+@pytest.mark.parametrize("seed", [7107, 7119, 7121, 7126, 7127, 7136])
+def test_seven_vertex_patterns_nonzero_labels(seed):
+    # size-7 codes fill 63 bits of the pattern key: with every label >= 5 the
+    # high bits are set, so nothing may read them as a graph id (these seeds
+    # have 11..1587 frequent size-7 patterns at t = 1)
+    s, d, lab = synth.tiny_graph(seed, 9, 16, 2)
+    lab = (lab + 5 + seed % 7).astype(np.int32)
+    n = len(lab)
+    say(f"size7 nonzero labels seed={seed} n={n} m={len(s)}")
+    want = oracle.mine(n, s, d, lab, 1, 7)
+    assert_same(gpu_mine(n, s, d, lab, 1, 7).patterns, want)
+    with fsm.Graph(n, s, d, lab) as g:
+        assert_same(fsm.mine_batch([g], [1], 7)[0].patterns, want)
+
+
+def test_seven_vertex_patterns_without_label_zero():
+    # a 7-cycle with two chords, all label 9, plus an edge of label 2: label 2
+    # takes frequent id 0, so every size-7 pattern here starts with id 1 and
+    # its key has bits >= 57 set
+    pairs = [(i, (i + 1) % 7) for i in range(7)] + [(0, 3), (2, 5), (7, 8)]
+    s, d = edges(pairs)
+    lab = np.array([9] * 7 + [2, 2], np.int32)
+    want = oracle.mine(9, s, d, lab, 1, 7)
+    assert sum(1 for p in want if p[0] == 7) > 0
+    say("size7 without label zero")
+    assert_same(gpu_mine(9, s, d, lab, 1, 7).patterns, want)
+    with fsm.Graph(9, s, d, lab) as g:
+        assert_same(fsm.mine_batch([g], [1], 7)[0].patterns, want)
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_seven_vertex_patterns_small_graphs(seed):
     s, d, lab = synth.tiny_graph(7000 + seed, 8, 12, 1 + seed % 2)
