@@ -70,7 +70,7 @@ typedef struct {
 enum {
     FSM_PLAIN = 0,    /* level-by-level exact join (Sections 3-4) */
     FSM_BATCHED = 1,  /* many graphs in one pass (fsm_mine_batch) */
-    FSM_LEARNED = 2,  /* reserved: learned cost model for sizing */
+    FSM_LEARNED = 2,  /* size join tables from a cost model (options.model) */
     FSM_SAMPLED = 4   /* subgraph sampling during joining (Section 5) */
 };
 
@@ -105,6 +105,8 @@ typedef struct {
     int64_t domain_passes;    /* domain passes run: 1 + reruns after the
                                  quick-pattern table overflowed */
     int64_t qp_capacity;      /* quick-pattern table slots of the last pass */
+    int64_t qp_predicted;     /* FSM_LEARNED join levels: the cost model's
+                                 estimate of quick_patterns (0 otherwise) */
 } fsm_level_stats;
 
 typedef struct {
@@ -139,6 +141,11 @@ typedef struct {
                                    (grown on overflow) */
     int64_t pattern_capacity_min;  /* >0: initial canonical-pattern table
                                       slots (grown on overflow) */
+    const struct fsm_model *model; /* FSM_LEARNED: cost model with
+                                      FSM_FEATURES inputs */
+    int32_t record;           /* 1: keep one training row per join work item
+                                 in the result (fsm_result_training_rows) */
+    int32_t reserved1;
 } fsm_options;
 
 /* Allocation hooks used for all device memory of later calls (e.g. a
@@ -222,6 +229,15 @@ typedef struct {
     int32_t reserved0;
     int64_t hash_capacity_min;  /* as fsm_options (first chunk) */
     int64_t pattern_capacity_min;
+    struct fsm_model *model;    /* FSM_LEARNED: cost model with FSM_FEATURES
+                                   inputs, used to size every chunk's join
+                                   tables */
+    int32_t learn;              /* 1: after each chunk, train the model on
+                                   that chunk's work items (train_steps Adam
+                                   steps at learning rate lr) */
+    int32_t train_steps;
+    float lr;
+    int32_t reserved1;
 } fsm_batch_options;
 
 /* fsm_mine_batch with options.  Graphs are ordered by their most populous
@@ -234,6 +250,84 @@ typedef struct {
 int fsm_mine_batch_ex(const fsm_graph *const *graphs, int32_t count,
                       const int64_t *supports, const fsm_batch_options *opt,
                       fsm_result **outs);
+
+/* Work-item features of the cost model (one row per join work item: a
+ * parent quick pattern P of size n-2 with embeddings, and the position i of
+ * the joining vertex in it), FSM_FEATURES float32 values:
+ *   0  n / 8                       3  log1p(mean G_f degree of the vertices
+ *   1  edges of P / pairs of P            at position i) / 8
+ *   2  log1p(embeddings of P) / 16 4  log1p(MNI support of P's pattern) / 16
+ *                                  5  log1p(support threshold) / 16
+ *   6 .. 21   label histogram of P (fraction of positions per frequent
+ *             label id, ids >= 15 share bucket 15)
+ *   22 .. 37  one-hot label bucket of position i
+ * Targets: log1p(children the join emits from the item), log1p(distinct
+ * child quick patterns).  Child quick patterns of different items are
+ * distinct, so the second target sums to the level's quick_patterns. */
+#define FSM_FEATURE_LABELS 16
+#define FSM_FEATURES (6 + 2 * FSM_FEATURE_LABELS)
+
+/* Training rows recorded by a call with options.record = 1 (-1 for NULL). */
+int64_t fsm_result_training_count(const fsm_result *r);
+
+/* Copy the recorded rows out: x (count x FSM_FEATURES), t (count x 2),
+ * level (count, the join size n of each row); any pointer may be NULL. */
+int fsm_result_training_rows(const fsm_result *r, float *x, float *t, int32_t *level);
+
+/* ---------------------------------------------------------------------
+ * Join cost model.  Not part of the paper's method: a two-layer perceptron
+ * that predicts, per join work item (a parent quick pattern and the joining
+ * position), log1p of the children the join emits from it and log1p of the
+ * distinct child quick patterns.  The miner records such rows itself
+ * (fsm_result_training_rows) and uses the predictions to size its tables and
+ * to order its work (FSM_LEARNED); it never changes a mined result.
+ *
+ * Shape: in_dim inputs (1..FSM_MODEL_MAX_IN), FSM_MODEL_HIDDEN ReLU units,
+ * FSM_MODEL_OUT linear outputs.  Parameters, float32, flat in this order:
+ * W1 (in_dim x 64, row-major), b1 (64), W2 (64 x 2, row-major), b2 (2);
+ * forward and backward passes read them rounded to bfloat16 (round to
+ * nearest even) and accumulate in float32; training updates float32 master
+ * copies with full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the loss
+ * sum((y - t)^2) / (2 rows).  All array arguments are host memory, row-major,
+ * copied during the call; the caller keeps ownership.
+ * ------------------------------------------------------------------- */
+typedef struct fsm_model fsm_model;
+
+#define FSM_MODEL_HIDDEN 64
+#define FSM_MODEL_OUT 2
+#define FSM_MODEL_MAX_IN 160
+
+/* Number of parameters of a model with in_dim inputs (-1 if out of range). */
+int64_t fsm_model_param_count(int32_t in_dim);
+
+/* New model on the current device.  params: fsm_model_param_count(in_dim)
+ * initial values, or NULL for the library's initialisation (uniform in
+ * +-1/sqrt(fan_in) from a splitmix64 stream seeded by seed, zero biases).
+ * Errors: FSM_EINVAL for in_dim out of range or NULL out. */
+int fsm_model_create(int32_t in_dim, const float *params, uint64_t seed, fsm_model **out);
+
+/* Inputs of a model (-1 for NULL). */
+int32_t fsm_model_in_dim(const fsm_model *m);
+
+/* Copy the float32 master parameters out (param_count values). */
+int fsm_model_params(const fsm_model *m, float *params);
+
+/* Gradient of the loss over rows (x: rows x in_dim, t: rows x 2) with
+ * respect to the bfloat16 parameter values, into grad (param_count values);
+ * loss (may be NULL) receives the loss.  Does not change the model. */
+int fsm_model_gradient(fsm_model *m, const float *x, const float *t, int64_t rows,
+                       float *grad, double *loss);
+
+/* steps full-batch Adam steps at learning rate lr on (x, t); loss (may be
+ * NULL) receives the loss of the last step's forward pass.  The optimiser
+ * state persists across calls. */
+int fsm_model_train(fsm_model *m, const float *x, const float *t, int64_t rows,
+                    int32_t steps, float lr, double *loss);
+
+/* Predictions y (rows x 2) for inputs x (rows x in_dim). */
+int fsm_model_predict(const fsm_model *m, const float *x, int64_t rows, float *y);
+
+void fsm_model_free(fsm_model *m);
 
 /* Number of frequent patterns in a result (-1 for NULL). */
 int64_t fsm_result_count(const fsm_result *r);

@@ -25,6 +25,8 @@ FSM_PLAIN = 0
 FSM_BATCHED = 1
 FSM_LEARNED = 2
 FSM_SAMPLED = 4
+FEATURE_LABELS = 16
+FEATURES = 6 + 2 * FEATURE_LABELS
 MAX_SIZE = 7
 
 STATUS = {0: "FSM_OK", -1: "FSM_EINVAL", -2: "FSM_ENOMEM", -3: "FSM_EDEVICE",
@@ -49,7 +51,8 @@ class LevelStats(ctypes.Structure):
                 ("frequent", ctypes.c_int64), ("stored", ctypes.c_int64),
                 ("algorithmic_bytes", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
-                ("domain_passes", ctypes.c_int64), ("qp_capacity", ctypes.c_int64)]
+                ("domain_passes", ctypes.c_int64), ("qp_capacity", ctypes.c_int64),
+                ("qp_predicted", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -67,7 +70,9 @@ class BatchOptions(ctypes.Structure):
     _fields_ = [("max_size", ctypes.c_int32), ("mode", ctypes.c_uint32),
                 ("chunk_vertices", ctypes.c_int64), ("disable_pruning", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("hash_capacity_min", ctypes.c_int64),
-                ("pattern_capacity_min", ctypes.c_int64)]
+                ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
+                ("learn", ctypes.c_int32), ("train_steps", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("reserved1", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):
@@ -75,7 +80,8 @@ class Options(ctypes.Structure):
                 ("mode", ctypes.c_uint32), ("disable_pruning", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
-                ("pattern_capacity_min", ctypes.c_int64)]
+                ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
+                ("record", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -128,6 +134,11 @@ def lib():
     L.fsm_mine_batch_ex.restype = ctypes.c_int
     L.fsm_result_count.argtypes = [vp]
     L.fsm_result_count.restype = ctypes.c_int64
+    L.fsm_result_training_count.argtypes = [vp]
+    L.fsm_result_training_count.restype = ctypes.c_int64
+    L.fsm_result_training_rows.argtypes = [vp, ctypes.POINTER(ctypes.c_float),
+                                           ctypes.POINTER(ctypes.c_float), i32p]
+    L.fsm_result_training_rows.restype = ctypes.c_int
     L.fsm_result_patterns.argtypes = [vp, i32p, i32p, ctypes.POINTER(Code), i64p]
     L.fsm_result_patterns.restype = ctypes.c_int
     L.fsm_result_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -141,6 +152,25 @@ def lib():
     L.fsm_dissect.argtypes = [ctypes.c_int32, i32p, ctypes.c_uint32,
                               ctypes.POINTER(ctypes.c_uint32), i32p]
     L.fsm_dissect.restype = ctypes.c_int
+    f32p = ctypes.POINTER(ctypes.c_float)
+    L.fsm_model_param_count.argtypes = [ctypes.c_int32]
+    L.fsm_model_param_count.restype = ctypes.c_int64
+    L.fsm_model_create.argtypes = [ctypes.c_int32, f32p, ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.fsm_model_create.restype = ctypes.c_int
+    L.fsm_model_in_dim.argtypes = [vp]
+    L.fsm_model_in_dim.restype = ctypes.c_int32
+    L.fsm_model_params.argtypes = [vp, f32p]
+    L.fsm_model_params.restype = ctypes.c_int
+    L.fsm_model_gradient.argtypes = [vp, f32p, f32p, ctypes.c_int64, f32p,
+                                     ctypes.POINTER(ctypes.c_double)]
+    L.fsm_model_gradient.restype = ctypes.c_int
+    L.fsm_model_train.argtypes = [vp, f32p, f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float,
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.fsm_model_train.restype = ctypes.c_int
+    L.fsm_model_predict.argtypes = [vp, f32p, ctypes.c_int64, f32p]
+    L.fsm_model_predict.restype = ctypes.c_int
+    L.fsm_model_free.argtypes = [vp]
+    L.fsm_model_free.restype = None
     _lib = L
     return L
 
@@ -256,6 +286,15 @@ class Result:
                 sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
             st = Stats()
             _check(L.fsm_result_stats(handle, ctypes.byref(st)))
+            nrow = L.fsm_result_training_count(handle)
+            self.train_x = np.zeros((nrow, FEATURES), np.float32)
+            self.train_t = np.zeros((nrow, 2), np.float32)
+            self.train_level = np.zeros(nrow, np.int32)
+            if nrow > 0:
+                _check(L.fsm_result_training_rows(
+                    handle, self.train_x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                    self.train_t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                    self.train_level.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         finally:
             L.fsm_result_free(handle)
         self.patterns = [(int(codes[i].n), tuple(int(codes[i].label[j]) for j in range(codes[i].n)),
@@ -278,9 +317,14 @@ def _stats_dict(st):
 
 def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
-         hash_capacity_min: int = 0, pattern_capacity_min: int = 0) -> Result:
-    """Frequent patterns of sizes 2..max_size with MNI support >= support."""
+         hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
+         record: bool = False) -> Result:
+    """Frequent patterns of sizes 2..max_size with MNI support >= support.
+    ``model`` (a Model with FEATURES inputs) sizes the join tables when
+    ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows."""
     o = Options()
+    o.model = model.handle.value if model is not None else None
+    o.record = 1 if record else 0
     o.support = int(support)
     o.max_size = int(max_size)
     o.mode = int(mode)
@@ -296,9 +340,12 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
 
 def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
                chunk_vertices: int = 0, disable_pruning: bool = False,
-               hash_capacity_min: int = 0, pattern_capacity_min: int = 0):
+               hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
+               learn: bool = False, train_steps: int = 0, lr: float = 0.0):
     """Mine several graphs in union passes of at most ``chunk_vertices``
-    vertices (0: the library default); one Result per graph."""
+    vertices (0: the library default); one Result per graph.  With a
+    ``model``, FSM_LEARNED in ``mode`` sizes every chunk's join tables from
+    it, and ``learn`` trains it on each chunk's work items."""
     n = len(graphs)
     if len(supports) != n:
         raise ValueError("one support per graph")
@@ -312,9 +359,88 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
     o.disable_pruning = 1 if disable_pruning else 0
     o.hash_capacity_min = int(hash_capacity_min)
     o.pattern_capacity_min = int(pattern_capacity_min)
+    o.model = model.handle.value if model is not None else None
+    o.learn = 1 if learn else 0
+    o.train_steps = int(train_steps)
+    o.lr = float(lr)
     _check(lib().fsm_mine_batch_ex(hs, n, sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    ctypes.byref(o), outs))
     return [Result(ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+def _f32(a, cols=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if cols is not None and (a.ndim != 2 or a.shape[1] != cols):
+        raise ValueError(f"expected a (rows, {cols}) array")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Model:
+    """Join cost model on the device (two-layer perceptron, bfloat16
+    weights, float32 accumulation); see ``fsm_model_*`` in include/fsm.h."""
+
+    HIDDEN = 64
+    OUT = 2
+
+    def __init__(self, in_dim: int, params=None, seed: int = 0):
+        L = lib()
+        self.in_dim = int(in_dim)
+        self.count = int(L.fsm_model_param_count(self.in_dim))
+        pp = None
+        if params is not None:
+            self._init, pp = _f32(params)
+            if self._init.size != self.count:
+                raise ValueError(f"expected {self.count} parameters")
+        h = ctypes.c_void_p()
+        _check(L.fsm_model_create(self.in_dim, pp, int(seed) & ((1 << 64) - 1), ctypes.byref(h)))
+        self.handle = h
+
+    def params(self):
+        out = np.empty(self.count, np.float32)
+        _check(lib().fsm_model_params(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def gradient(self, x, t):
+        x, xp = _f32(x, self.in_dim)
+        t, tp = _f32(t, self.OUT)
+        g = np.empty(self.count, np.float32)
+        loss = ctypes.c_double()
+        _check(lib().fsm_model_gradient(self.handle, xp, tp, len(x),
+                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, x, t, steps: int, lr: float) -> float:
+        x, xp = _f32(x, self.in_dim)
+        t, tp = _f32(t, self.OUT)
+        loss = ctypes.c_double()
+        _check(lib().fsm_model_train(self.handle, xp, tp, len(x), int(steps), float(lr),
+                                     ctypes.byref(loss)))
+        return loss.value
+
+    def predict(self, x):
+        x, xp = _f32(x, self.in_dim)
+        y = np.empty((len(x), self.OUT), np.float32)
+        _check(lib().fsm_model_predict(self.handle, xp, len(x),
+                                       y.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fsm_model_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def dissect(ids, adj):

@@ -8,6 +8,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "model.h"
 
 namespace fsm {
 namespace {
@@ -146,8 +147,14 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
         if (opt->support < 1) fail(FSM_EINVAL, "fsm_mine: support must be >= 1");
         if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
             fail(FSM_EINVAL, "fsm_mine: max_size must be in [2, %d]", FSM_MAX_SIZE);
-        if (opt->mode & ~(uint32_t)FSM_SAMPLED)
+        if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED))
             fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
+        if ((opt->mode & FSM_LEARNED) && !opt->model)
+            fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
+        if (opt->model && opt->model->m.D != FSM_FEATURES)
+            fail(FSM_EINVAL, "fsm_mine: the model must have FSM_FEATURES (%d) inputs", FSM_FEATURES);
+        if (opt->model && opt->model->device != g->device)
+            fail(FSM_EINVAL, "fsm_mine: model and graph live on different devices");
         if ((opt->mode & FSM_SAMPLED) &&
             !(opt->sampling_rate > 0.0 && opt->sampling_rate <= 1.0))
             fail(FSM_EINVAL, "fsm_mine: sampling_rate must be in (0, 1]");
@@ -190,9 +197,16 @@ int fsm_mine_batch_ex(const fsm_graph* const* graphs, int32_t count, const int64
         if (count > 2048) fail(FSM_EUNSUPPORTED, "fsm_mine_batch: at most 2048 graphs");
         if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
             fail(FSM_EINVAL, "fsm_mine_batch: max_size must be in [2, %d]", FSM_MAX_SIZE);
-        if (opt->mode & ~(uint32_t)FSM_BATCHED)
+        if (opt->mode & ~(uint32_t)(FSM_BATCHED | FSM_LEARNED))
             fail(FSM_EINVAL, "fsm_mine_batch: unsupported mode bits 0x%x", opt->mode);
         if (opt->chunk_vertices < 0) fail(FSM_EINVAL, "fsm_mine_batch: chunk_vertices < 0");
+        if (((opt->mode & FSM_LEARNED) || opt->learn) && !opt->model)
+            fail(FSM_EINVAL, "fsm_mine_batch: FSM_LEARNED and learn need a model");
+        if (opt->model && opt->model->m.D != FSM_FEATURES)
+            fail(FSM_EINVAL, "fsm_mine_batch: the model must have FSM_FEATURES (%d) inputs",
+                 FSM_FEATURES);
+        if (opt->train_steps < 0 || opt->lr < 0.f)
+            fail(FSM_EINVAL, "fsm_mine_batch: train_steps and lr must be >= 0");
         for (int32_t i = 0; i < count; ++i) {
             if (!graphs[i]) fail(FSM_EINVAL, "fsm_mine_batch: graph %d is NULL", i);
             if (supports[i] < 1) fail(FSM_EINVAL, "fsm_mine_batch: support %d must be >= 1", i);
@@ -221,6 +235,17 @@ int fsm_mine_batch(const fsm_graph* const* graphs, int32_t count, const int64_t*
 
 int64_t fsm_result_count(const fsm_result* r) { return r ? (int64_t)r->size.size() : -1; }
 
+int64_t fsm_result_training_count(const fsm_result* r) { return r ? (int64_t)r->tl.size() : -1; }
+
+int fsm_result_training_rows(const fsm_result* r, float* x, float* t, int32_t* level) {
+    return guarded([&] {
+        if (!r) fail(FSM_EINVAL, "fsm_result_training_rows: NULL result");
+        if (x && !r->tx.empty()) memcpy(x, r->tx.data(), sizeof(float) * r->tx.size());
+        if (t && !r->tt.empty()) memcpy(t, r->tt.data(), sizeof(float) * r->tt.size());
+        if (level && !r->tl.empty()) memcpy(level, r->tl.data(), sizeof(int32_t) * r->tl.size());
+    });
+}
+
 int fsm_result_patterns(const fsm_result* r, int32_t* ids, int32_t* sizes, fsm_code* codes,
                         int64_t* supports) {
     return guarded([&] {
@@ -243,6 +268,87 @@ int fsm_result_stats(const fsm_result* r, fsm_stats* s) {
 
 void fsm_graph_free(fsm_graph* g) { delete g; }
 void fsm_result_free(fsm_result* r) { delete r; }
+
+int64_t fsm_model_param_count(int32_t in_dim) {
+    if (in_dim < 1 || in_dim > MODEL_MAX_IN) return -1;
+    return model_param_count(in_dim);
+}
+
+int fsm_model_create(int32_t in_dim, const float* params, uint64_t seed, fsm_model** out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out) fail(FSM_EINVAL, "fsm_model_create: out is NULL");
+        if (in_dim < 1 || in_dim > MODEL_MAX_IN)
+            fail(FSM_EINVAL, "fsm_model_create: in_dim must be in [1, %d]", MODEL_MAX_IN);
+        int dev = 0;
+        FSM_HIP(hipGetDevice(&dev));
+        fsm_model* m = new fsm_model(in_dim, params, seed);
+        m->device = dev;
+        *out = m;
+    });
+}
+
+int32_t fsm_model_in_dim(const fsm_model* m) { return m ? m->m.D : -1; }
+
+int fsm_model_params(const fsm_model* m, float* params) {
+    return guarded([&] {
+        if (!m || !params) fail(FSM_EINVAL, "fsm_model_params: NULL argument");
+        m->m.params(params);
+    });
+}
+
+namespace {
+// host rows -> device copies for one model call
+struct Rows {
+    DBuf<float> x, t;
+    Rows(const fsm_model* m, const float* hx, const float* ht, int64_t rows, const char* who) {
+        if (!m || !hx || rows < 0) fail(FSM_EINVAL, "%s: NULL model/x or rows < 0", who);
+        if (rows > ((int64_t)1 << 31) / m->m.D) fail(FSM_EUNSUPPORTED, "%s: too many rows", who);
+        x.alloc((size_t)(rows * m->m.D));
+        to_device(x.p, hx, (size_t)(rows * m->m.D));
+        if (ht) {
+            t.alloc((size_t)(rows * MODEL_OUT));
+            to_device(t.p, ht, (size_t)(rows * MODEL_OUT));
+        }
+    }
+};
+}  // namespace
+
+int fsm_model_gradient(fsm_model* m, const float* x, const float* t, int64_t rows, float* grad,
+                       double* loss) {
+    return guarded([&] {
+        if (!t || !grad) fail(FSM_EINVAL, "fsm_model_gradient: NULL t/grad");
+        Rows r(m, x, t, rows, "fsm_model_gradient");
+        const float l = m->m.gradient(r.x.p, r.t.p, rows);
+        FSM_HIP(hipMemcpyAsync(grad, m->m.g.p, sizeof(float) * (size_t)m->m.n,
+                               hipMemcpyDeviceToHost, stream()));
+        FSM_HIP(hipStreamSynchronize(stream()));
+        if (loss) *loss = l;
+    });
+}
+
+int fsm_model_train(fsm_model* m, const float* x, const float* t, int64_t rows, int32_t steps,
+                    float lr, double* loss) {
+    return guarded([&] {
+        if (!t) fail(FSM_EINVAL, "fsm_model_train: NULL t");
+        if (steps < 0 || !(lr > 0.f)) fail(FSM_EINVAL, "fsm_model_train: steps < 0 or lr <= 0");
+        Rows r(m, x, t, rows, "fsm_model_train");
+        const float l = m->m.train(r.x.p, r.t.p, rows, steps, lr);
+        if (loss) *loss = l;
+    });
+}
+
+int fsm_model_predict(const fsm_model* m, const float* x, int64_t rows, float* y) {
+    return guarded([&] {
+        if (!y) fail(FSM_EINVAL, "fsm_model_predict: NULL y");
+        Rows r(m, x, nullptr, rows, "fsm_model_predict");
+        DBuf<float> dy((size_t)(rows * MODEL_OUT));
+        m->m.predict(r.x.p, rows, dy.p);
+        to_host_into(y, dy.p, (size_t)(rows * MODEL_OUT));
+    });
+}
+
+void fsm_model_free(fsm_model* m) { delete m; }
 
 const char* fsm_last_error(void) { return g_err; }
 

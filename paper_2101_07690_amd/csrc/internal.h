@@ -84,6 +84,12 @@ void to_host(std::vector<T>& h, const T* d, size_t count) {
 }
 
 template <class T>
+void to_host_into(T* h, const T* d, size_t count) {
+    if (count) FSM_HIP(hipMemcpyAsync(h, d, count * sizeof(T), hipMemcpyDeviceToHost, stream()));
+    FSM_HIP(hipStreamSynchronize(stream()));
+}
+
+template <class T>
 T scalar_to_host(const T* d) {
     T v;
     FSM_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, stream()));
@@ -128,6 +134,8 @@ struct fsm_result {
     std::vector<fsm_code> code;
     std::vector<int64_t> support;
     fsm_stats stats{};
+    std::vector<float> tx, tt;      // recorded work-item rows: features, targets
+    std::vector<int32_t> tl;        // join size of each row
 };
 
 namespace fsm {

@@ -34,6 +34,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "model.h"
 
 namespace fsm {
 namespace {
@@ -77,6 +78,7 @@ struct Rec {
     Pool pool;
     uint32_t* flags;
     int n;             // subgraph size of this level
+    unsigned* item_qps = nullptr;   // join levels, when recording: new QPs per work item
 };
 
 // ---------------------------------------------------------------- helpers
@@ -151,6 +153,9 @@ __device__ __forceinline__ int64_t qp_slot(const Rec& R, uint64_t key, uint64_t 
             if (prev == EMPTY_KEY) {
                 R.q.adj[h] = A;
                 R.q.lab[h] = L;
+                // join keys: parent slot << 35 | position << 32 | ...
+                if (R.item_qps)
+                    atomicAdd(&R.item_qps[(key >> 35) * (uint64_t)(R.n - 2) + ((key >> 32) & 7u)], 1u);
                 const unsigned c = atomicAdd(R.q.count, 1u);
                 if ((uint64_t)c * 2 > R.q.mask) atomicOr(R.flags, OVF_QP);
                 return (int64_t)h;
@@ -914,6 +919,7 @@ struct TileArgs {
     int prune;
     const Rec* rec;          // QP table (insert path)
     const uint32_t* flags;   // overflow / error bits of the pass
+    unsigned long long* item_children;   // when recording: children per work item
     unsigned long long* ctr; // [emitted, candidates, -, bytes]
     int sampled;
     uint64_t seed;
@@ -1197,27 +1203,33 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
                 if (j != i) mu = min(mu, cv[j]);
             }
             if (lane == 0) bytes += 4ull * (M + 1);
-            if (!types) continue;
-            bool ok = true;
+            const int32_t pslot = prow[M];
+            bool ok = types != 0;
 #pragma unroll
             for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
             // n <= 5: the smallest vertex of every child lies in the accepted
             // size-3 part (exhaustively true for connected graphs on 4 and 5
             // vertices), so a piece above min(parent \ k) is rejected
             if (N <= 5 && qmin > mu) ok = false;
-            if (!ok) continue;
-            const int32_t pslot = prow[M];
-            const uint64_t PA = a.padj[pslot];
-            cv[M] = u;
-            cv[M + 1] = w;
-            const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
-            const uint64_t Lc =
-                L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
-            lr[M] = lru;
-            lr[M + 1] = lrw;
-            const int got = children_tile<N>(a, f3, cv, lr, i, types, ec, PA, Lc, pslot, lu, lw, c);
-            emit += (unsigned long long)got;
-            bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
+            int got = 0;
+            if (ok) {
+                const uint64_t PA = a.padj[pslot];
+                cv[M] = u;
+                cv[M + 1] = w;
+                const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
+                const uint64_t Lc =
+                    L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
+                lr[M] = lru;
+                lr[M + 1] = lrw;
+                got = children_tile<N>(a, f3, cv, lr, i, types, ec, PA, Lc, pslot, lu, lw, c);
+                emit += (unsigned long long)got;
+                bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
+            }
+            if (a.item_children) {   // uniform: every lane is on parent pp
+                const int64_t sg = wave_sum((int64_t)got);
+                if (lane == 0 && sg)
+                    atomicAdd(&a.item_children[(int64_t)pslot * M + i], (unsigned long long)sg);
+            }
         }
     }
     const int64_t te = wave_sum((int64_t)emit);
@@ -1372,6 +1384,98 @@ __global__ void k_mark_frequent(QPTab q, uint64_t slots, const uint64_t* ckv, co
         const int32_t p = q.pat[s];
         if (sup[p] >= tg[code_graph(ckv[2 * p], n)]) q.kv[2 * s + 1] = v | FREQ;
     }
+}
+
+// ------------------------------------------------ cost-model work items
+//
+// A work item of the size-n join is (parent QP slot s, joining position i);
+// its id is s * (n - 2) + i.  Child QP keys start with (s, i), so the items'
+// child QP sets are disjoint and sum to the level's QP count.
+
+// Parent embeddings per QP slot and the G_f degree sum of each position.
+__global__ void k_item_stats(const int32_t* par, int64_t rows, int M, const int32_t* frow,
+                             unsigned* cnt, float* degsum) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* pr = par + r * (M + 1);
+        const int64_t s = pr[M];
+        atomicAdd(&cnt[s], 1u);
+        for (int i = 0; i < M; ++i)
+            atomicAdd(&degsum[s * M + i], (float)(frow[pr[i] + 1] - frow[pr[i]]));
+    }
+}
+
+__global__ void k_item_flags(const unsigned* cnt, int64_t items, int M, int64_t* flag) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < items;
+         x += (int64_t)gridDim.x * blockDim.x)
+        flag[x] = cnt[x / M] ? 1 : 0;
+}
+
+struct FeatArgs {
+    const int64_t* pos;      // exclusive scan of the item flags
+    int32_t* graph;          // rows: graph id of the item (batches)
+    const unsigned* cnt;
+    const float* degsum;
+    const uint64_t* qadj;    // parent QP tables
+    const uint64_t* qlab;
+    const int32_t* qpat;
+    const int64_t* csup;
+    const int64_t* tg;
+    int64_t items;
+    int M, n;
+    float* x;                // rows x FSM_FEATURES
+    int32_t* item;           // rows
+};
+
+// Features of every item with parent embeddings, at row pos[item] (the
+// layout fsm.h documents under FSM_FEATURES).
+__global__ void k_item_features(FeatArgs a) {
+    for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < a.items;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = it / a.M;
+        const int i = (int)(it - s * a.M);
+        const unsigned c = a.cnt[s];
+        if (!c) continue;
+        float* x = a.x + a.pos[it] * FSM_FEATURES;
+        a.item[a.pos[it]] = (int32_t)it;
+        const uint64_t L = a.qlab[s];
+        a.graph[a.pos[it]] = (int32_t)(L >> 48);
+        const int npairs = a.M * (a.M - 1) / 2;
+        x[0] = (float)a.n / 8.0f;
+        x[1] = (float)(__popcll(a.qadj[s]) / 2) / (float)(npairs > 0 ? npairs : 1);
+        x[2] = log1pf((float)c) / 16.0f;
+        x[3] = log1pf(a.degsum[it] / (float)c) / 8.0f;
+        x[4] = log1pf((float)a.csup[a.qpat[s]]) / 16.0f;
+        x[5] = log1pf((float)a.tg[L >> 48]) / 16.0f;
+        for (int b = 0; b < 2 * FSM_FEATURE_LABELS; ++b) x[6 + b] = 0.0f;
+        for (int p = 0; p < a.M; ++p) {
+            const int l = min(lab_at(L, p), FSM_FEATURE_LABELS - 1);
+            x[6 + l] += 1.0f / (float)a.M;
+            if (p == i) x[6 + FSM_FEATURE_LABELS + l] = 1.0f;
+        }
+    }
+}
+
+// Targets of every row: log1p(children), log1p(child QPs) of its item.
+__global__ void k_item_targets(const int32_t* item, int64_t rows,
+                               const unsigned long long* children, const unsigned* qps, float* t) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t it = item[r];
+        t[2 * r] = log1pf((float)children[it]);
+        t[2 * r + 1] = log1pf((float)qps[it]);
+    }
+}
+
+// Sum of expm1 of one prediction column (the predicted level total).
+__global__ void k_pred_total(const float* y, int64_t rows, int col, double* out) {
+    double acc = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x)
+        acc += expm1((double)fmaxf(y[2 * r + col], 0.0f));
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(out, acc);
 }
 
 // ================================================================== host
@@ -1570,6 +1674,18 @@ struct Miner {
     std::vector<fsm_result*> res;         // one per graph
 
     uint64_t qhint[FSM_MAX_SIZE + 1] = {};   // first QP table size per level (0: default)
+    const Model* model = nullptr;          // FSM_LEARNED: sizes the join tables
+    std::vector<float> rx, rt;             // recorded work-item rows (features, targets)
+    std::vector<int32_t> rl, rg;           // their join size and graph id
+
+    // work items of the size-n join: features of every (parent QP, position)
+    // with parent embeddings
+    struct ItemRows {
+        DBuf<float> x;
+        DBuf<int32_t> item, graph;
+        int64_t rows = 0;
+    };
+    void item_rows(const Level& P, int n, ItemRows& IR);
 
     uint64_t qcap0() const {
         uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 14);
@@ -1870,6 +1986,28 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G) {
     FSM_HIP(hipStreamSynchronize(st));
 }
 
+void Miner::item_rows(const Level& P, int n, ItemRows& IR) {
+    const int M = n - 2;
+    const int64_t nitems = (int64_t)P.tab.qcap * M;
+    DBuf<unsigned> cnt((size_t)P.tab.qcap);
+    DBuf<float> dsum((size_t)nitems);
+    cnt.zero();
+    dsum.zero();
+    k_item_stats<<<grid_for(P.rows, TPB), TPB, 0, st>>>(P.emb.p, P.rows, M, frow.p, cnt.p, dsum.p);
+    FSM_LAUNCH_CHECK();
+    DBuf<int64_t> pos((size_t)nitems);
+    k_item_flags<<<grid_for(nitems, TPB), TPB, 0, st>>>(cnt.p, nitems, M, pos.p);
+    FSM_LAUNCH_CHECK();
+    IR.rows = scan_exclusive(pos.p, pos.p, nitems);
+    IR.x.alloc((size_t)(IR.rows * FSM_FEATURES));
+    IR.item.alloc((size_t)IR.rows);
+    IR.graph.alloc((size_t)IR.rows);
+    FeatArgs fa{pos.p, IR.graph.p, cnt.p, dsum.p, P.tab.qadj.p, P.tab.qlab.p, P.tab.qpat.p,
+                P.tab.csup.p, dtg.p, nitems, M, n, IR.x.p, IR.item.p};
+    k_item_features<<<grid_for(nitems, TPB), TPB, 0, st>>>(fa);
+    FSM_LAUNCH_CHECK();
+}
+
 void Miner::join(int n) {
     Level& L = lv[n];
     Level& P = lv[n - 2];
@@ -1878,6 +2016,31 @@ void Miner::join(int n) {
     const int64_t nwork = P.rows * M;
     L.st.parents = P.rows;
     L.st.work_items = nwork;
+    // cost-model work items: predictions size the QP table; recorded
+    // targets come from the domain pass
+    const bool learned = (opt.mode & FSM_LEARNED) && model != nullptr;
+    const bool record = opt.record != 0;
+    ItemRows IR;
+    if ((learned || record) && P.rows > 0) item_rows(P, n, IR);
+    if (learned && IR.rows > 0) {
+        DBuf<float> y((size_t)(IR.rows * MODEL_OUT));
+        model->predict(IR.x.p, IR.rows, y.p);
+        DBuf<double> tot(1);
+        tot.zero();
+        k_pred_total<<<grid_for(IR.rows, TPB, 1024), TPB, 0, st>>>(y.p, IR.rows, 1, tot.p);
+        FSM_LAUNCH_CHECK();
+        const double pq = scalar_to_host(tot.p);
+        L.st.qp_predicted = (int64_t)std::llround(pq);
+        // load <= 1/2, 25% slack; an underestimate still overflows and reruns
+        qhint[n] = pow2_at_least((uint64_t)(2.5 * pq) + 64);
+    }
+    const int64_t nitems = (int64_t)P.tab.qcap * M;
+    DBuf<unsigned long long> ich;
+    DBuf<unsigned> iqp;
+    if (record && IR.rows > 0) {
+        ich.alloc((size_t)nitems);
+        iqp.alloc((size_t)nitems);
+    }
     const uint64_t thr =
         opt.sampling_rate >= 1.0 ? ~0ull
                                  : (uint64_t)std::ldexp(opt.sampling_rate, 64);
@@ -1934,6 +2097,7 @@ void Miner::join(int n) {
         t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p;
         t.tile_p = G.tile_p;
         t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p; t.flags = R.flags;
+        t.item_children = nullptr;
         t.ctr = counters.p;
         t.prune = opt.disable_pruning ? 0 : 1;
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
@@ -1946,9 +2110,15 @@ void Miner::join(int n) {
     FSM_HIP(hipEventCreate(&j1));
     try {
         domain_level(L, [&](Rec R) {
+            if (ich.p) {
+                ich.zero();
+                iqp.zero();
+                R.item_qps = iqp.p;
+            }
             FSM_HIP(hipEventRecord(j0, st));
             if (G.ntiles > 0) {
-                const TileArgs t = tile_args(R);
+                TileArgs t = tile_args(R);
+                t.item_children = ich.p;
                 switch (n) {
                     case 4: k_join_tiles<4><<<grid_persistent, TPB, 0, st>>>(t); break;
                     case 5: k_join_tiles<5><<<grid_persistent, TPB, 0, st>>>(t); break;
@@ -1971,6 +2141,20 @@ void Miner::join(int n) {
     }
     (void)hipEventDestroy(j0);
     (void)hipEventDestroy(j1);
+    if (ich.p) {
+        DBuf<float> t((size_t)(IR.rows * MODEL_OUT));
+        k_item_targets<<<grid_for(IR.rows, TPB), TPB, 0, st>>>(IR.item.p, IR.rows, ich.p, iqp.p,
+                                                               t.p);
+        FSM_LAUNCH_CHECK();
+        const size_t o = rt.size() / MODEL_OUT;
+        rx.resize((o + (size_t)IR.rows) * FSM_FEATURES);
+        rt.resize((o + (size_t)IR.rows) * MODEL_OUT);
+        rg.resize(o + (size_t)IR.rows);
+        to_host_into(rx.data() + o * FSM_FEATURES, IR.x.p, (size_t)IR.rows * FSM_FEATURES);
+        to_host_into(rt.data() + o * MODEL_OUT, t.p, (size_t)IR.rows * MODEL_OUT);
+        to_host_into(rg.data() + o, IR.graph.p, (size_t)IR.rows);
+        rl.resize(o + (size_t)IR.rows, n);
+    }
     if (n + 2 <= opt.max_size) {
         materialize(L, nwork, [&](int mode, int64_t* counts, const int64_t* offsets, int32_t* out,
                                   int64_t rows) {
@@ -1980,6 +2164,17 @@ void Miner::join(int n) {
 }
 
 void Miner::emit_results() {
+    if (opt.record) {
+        const size_t rows = rl.size();
+        for (size_t r = 0; r < rows; ++r) {
+            fsm_result* out = res[(size_t)rg[r]];
+            out->tx.insert(out->tx.end(), rx.begin() + (long)(r * FSM_FEATURES),
+                           rx.begin() + (long)((r + 1) * FSM_FEATURES));
+            out->tt.insert(out->tt.end(), rt.begin() + (long)(r * MODEL_OUT),
+                           rt.begin() + (long)((r + 1) * MODEL_OUT));
+            out->tl.push_back(rl[r]);
+        }
+    }
     for (int n = 2; n <= opt.max_size; ++n) {
         const int npairs = n * (n - 1) / 2;
         for (auto& kv : lv[n].freq) {
@@ -2131,6 +2326,7 @@ void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r) {
     Miner m;
     m.gv.single(g);
     m.opt = opt;
+    m.model = opt.model ? &opt.model->m : nullptr;
     m.tg.assign(1, opt.support);
     m.res.assign(1, r);
     r->stats.dropped_self_loops = g->dropped_loops;
@@ -2172,7 +2368,9 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
     fsm_options o;
     memset(&o, 0, sizeof(o));
     o.max_size = bo.max_size;
-    o.mode = FSM_PLAIN;
+    o.mode = bo.mode & FSM_LEARNED;
+    o.model = bo.model;
+    o.record = bo.learn && bo.model ? 1 : 0;
     o.disable_pruning = bo.disable_pruning;
     o.sampling_rate = 1.0;
     o.hash_capacity_min = bo.hash_capacity_min;
@@ -2195,6 +2393,7 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
         }
         Miner m;
         m.opt = o;
+        m.model = bo.model ? &bo.model->m : nullptr;
         for (int n = 2; n <= FSM_MAX_SIZE; ++n)
             if (qpv[n] > 0) m.qhint[n] = pow2_at_least((uint64_t)(2.5 * qpv[n] * (double)nv) + 16);
         try {
@@ -2215,6 +2414,16 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
         }
         for (int n = 2; n <= o.max_size; ++n)
             qpv[n] = std::max(qpv[n], (double)m.lv[n].st.quick_patterns / (double)std::max<int64_t>(nv, 1));
+        // online learning: the next chunks are sized by a model that has
+        // seen this chunk's work items
+        if (bo.learn && bo.model && !m.rl.empty()) {
+            const int64_t rows = (int64_t)m.rl.size();
+            DBuf<float> x((size_t)rows * FSM_FEATURES), t((size_t)rows * MODEL_OUT);
+            to_device(x.p, m.rx.data(), m.rx.size());
+            to_device(t.p, m.rt.data(), m.rt.size());
+            bo.model->m.train(x.p, t.p, rows, bo.train_steps > 0 ? bo.train_steps : 200,
+                              bo.lr > 0.f ? bo.lr : 3e-3f);
+        }
         for (int32_t i : part) chunk_of[(size_t)i] = chunk;
         ++chunk;
     }

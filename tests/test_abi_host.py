@@ -221,3 +221,15 @@ def test_mine_batch_ex_rejects_bad_options():
     assert b"mode" in L.fsm_last_error()
     assert L.fsm_mine_batch_ex(hs, 1, sup, None, outs) == -1
     assert outs[0] is None
+
+
+def test_model_shape_validation():
+    L = fsm.lib()
+    assert L.fsm_model_param_count(fsm.FEATURES) == fsm.FEATURES * 64 + 64 + 128 + 2
+    assert L.fsm_model_param_count(0) == -1 and L.fsm_model_param_count(161) == -1
+    for bad in (0, 161):
+        with pytest.raises(fsm.FsmError) as e:
+            fsm.Model(bad)
+        assert e.value.code == -1
+    text = open(os.path.join(ROOT, "include", "fsm.h")).read()
+    assert "#define FSM_FEATURE_LABELS 16" in text and fsm.FEATURES == 6 + 2 * 16
