@@ -74,6 +74,15 @@ enum {
     FSM_SAMPLED = 4   /* subgraph sampling during joining (Section 5) */
 };
 
+/* Join tile schedules (fsm_options.schedule).  Results never depend on it. */
+enum {
+    FSM_SCHEDULE_QUEUE = 0,   /* waves take the next tile from a device counter;
+                                 FSM_LEARNED orders the tiles by predicted cost,
+                                 largest first */
+    FSM_SCHEDULE_STATIC = 1   /* wave w of W takes tiles w, w+W, w+2W, ... in
+                                 joining-vertex order */
+};
+
 typedef enum {
     FSM_OK = 0,
     FSM_EINVAL = -1,       /* invalid argument; nothing was done */
@@ -133,7 +142,8 @@ typedef struct {
     uint32_t mode;            /* FSM_PLAIN or FSM_SAMPLED */
     int32_t disable_pruning;  /* 1: skip the Section 4.5 pruning (results
                                  are identical; counters differ) */
-    int32_t reserved0;
+    int32_t schedule;         /* join tile schedule: FSM_SCHEDULE_QUEUE
+                                 (0, default) or FSM_SCHEDULE_STATIC */
     double sampling_rate;     /* FSM_SAMPLED: keep probability of a size-3
                                  piece per key group, in (0, 1] */
     uint64_t seed;            /* FSM_SAMPLED: hash seed */

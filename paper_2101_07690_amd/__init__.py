@@ -25,6 +25,8 @@ FSM_PLAIN = 0
 FSM_BATCHED = 1
 FSM_LEARNED = 2
 FSM_SAMPLED = 4
+FSM_SCHEDULE_QUEUE = 0
+FSM_SCHEDULE_STATIC = 1
 FEATURE_LABELS = 16
 FEATURES = 6 + 2 * FEATURE_LABELS
 MAX_SIZE = 7
@@ -78,7 +80,7 @@ class BatchOptions(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("support", ctypes.c_int64), ("max_size", ctypes.c_int32),
                 ("mode", ctypes.c_uint32), ("disable_pruning", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("record", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
@@ -318,13 +320,14 @@ def _stats_dict(st):
 def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
          hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
-         record: bool = False) -> Result:
+         record: bool = False, schedule: int = FSM_SCHEDULE_QUEUE) -> Result:
     """Frequent patterns of sizes 2..max_size with MNI support >= support.
     ``model`` (a Model with FEATURES inputs) sizes the join tables when
     ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows."""
     o = Options()
     o.model = model.handle.value if model is not None else None
     o.record = 1 if record else 0
+    o.schedule = int(schedule)
     o.support = int(support)
     o.max_size = int(max_size)
     o.mode = int(mode)
@@ -441,6 +444,36 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+def score_sampled(exact, sampled):
+    """Score a sampled mining result against the exact one (lists of
+    ``(size, labels, adj, support)``).  Sampled embeddings are a subset of
+    the exact ones, so every sampled support is a lower bound of the exact
+    support and every reported pattern is truly frequent; the score states
+    how much of the exact answer the sample recovers:
+
+    ``recall``          found / exact frequent patterns
+    ``precision``       reported patterns that are exactly frequent
+    ``support_ratio``   mean of estimated / exact support over found patterns
+    ``lower_bound``     True when no estimate exceeds its exact support
+    ``by_size``         recall per pattern size
+    """
+    ex = {(p[0], tuple(p[1]), p[2]): p[3] for p in exact}
+    sm = {(p[0], tuple(p[1]), p[2]): p[3] for p in sampled}
+    found = [k for k in sm if k in ex]
+    ratios = [sm[k] / ex[k] for k in found]
+    sizes = sorted({k[0] for k in ex})
+    by_size = {}
+    for n in sizes:
+        tot = sum(1 for k in ex if k[0] == n)
+        by_size[n] = sum(1 for k in found if k[0] == n) / tot if tot else 1.0
+    return {"exact": len(ex), "reported": len(sm), "found": len(found),
+            "recall": len(found) / len(ex) if ex else 1.0,
+            "precision": len(found) / len(sm) if sm else 1.0,
+            "support_ratio": float(np.mean(ratios)) if ratios else 0.0,
+            "lower_bound": all(sm[k] <= ex[k] for k in found),
+            "by_size": by_size}
 
 
 def dissect(ids, adj):

@@ -151,6 +151,8 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
             fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
         if ((opt->mode & FSM_LEARNED) && !opt->model)
             fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
+        if (opt->schedule != FSM_SCHEDULE_QUEUE && opt->schedule != FSM_SCHEDULE_STATIC)
+            fail(FSM_EINVAL, "fsm_mine: unknown schedule %d", opt->schedule);
         if (opt->model && opt->model->m.D != FSM_FEATURES)
             fail(FSM_EINVAL, "fsm_mine: the model must have FSM_FEATURES (%d) inputs", FSM_FEATURES);
         if (opt->model && opt->model->device != g->device)

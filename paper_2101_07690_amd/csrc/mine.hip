@@ -559,6 +559,7 @@ struct JoinArgs {
     int sampled;
     uint64_t seed;
     uint64_t sample_thr;     // keep a piece when its hash is below this
+    const uint64_t* item_thr;   // or, when set, below the threshold of its work item
     int64_t* counts;
     const int64_t* offsets;
     int32_t* out;
@@ -676,6 +677,7 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
             for (int j = 0; j < M; ++j) cv[j] = prow[j];
             const int32_t pslot = prow[M];
             const uint64_t PA = a.padj[pslot];
+            const uint64_t sthr = a.item_thr ? a.item_thr[(int64_t)pslot * M + i] : a.sample_thr;
             int32_t k = cv[0], mu = INT_MAX;
             uint64_t L = 0;
 #pragma unroll
@@ -725,9 +727,7 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                     // connected graphs on 4 and 5 vertices), so a piece whose
                     // three vertices all exceed min(parent \ k) is rejected
                     if (N <= 5 && ok && min(k, min(u, w)) > mu) ok = false;
-                    if (ok && a.sampled &&
-                        sample_hash(a.seed, N, k, u, w) >= a.sample_thr)
-                        ok = false;
+                    if (ok && a.sampled && sample_hash(a.seed, N, k, u, w) >= sthr) ok = false;
                     if (ok) {
                         const int lu = a.vf[u], lw = a.vf[w];
                         if (centre) {
@@ -920,10 +920,13 @@ struct TileArgs {
     const Rec* rec;          // QP table (insert path)
     const uint32_t* flags;   // overflow / error bits of the pass
     unsigned long long* item_children;   // when recording: children per work item
+    int queue;               // 1: waves take tiles from a device counter (ctr[2]);
+                             // 0: wave w takes tiles w, w + waves, ...
     unsigned long long* ctr; // [emitted, candidates, -, bytes]
     int sampled;
     uint64_t seed;
     uint64_t sample_thr;
+    const uint64_t* item_thr;   // per work item sampling thresholds, or null
 };
 
 constexpr uint32_t RANK_MASK = (1u << 26) - 1;
@@ -1111,7 +1114,16 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
     unsigned long long emit = 0, cands = 0, bytes = 0;
     LaneCache c{EMPTY_KEY, 0, EMPTY_KEY, 0, 0, 0};
     int64_t g = 0;
-    for (int64_t t = wave_id_global(); t < a.ntiles; t += nw) {
+    int64_t run_item = -1, run_sum = 0;   // recording: children of the current item run
+    for (int64_t t = a.queue ? -1 : wave_id_global() - nw;;) {
+        if (a.queue) {
+            unsigned long long nt = 0;
+            if (lane == 0) nt = atomicAdd(&a.ctr[2], 1ull);
+            t = (int64_t)__shfl(nt, 0, 64);
+        } else {
+            t += nw;
+        }
+        if (t >= a.ntiles) break;
         // an overflowed pass is rerun with a larger table: stop early
         if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & OVF_QP)
             break;
@@ -1140,6 +1152,7 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
         const uint8_t* f3 = a.f3 + (size_t)gid * 2 * a.F * a.F * a.F;
         // this lane's piece
         int32_t u = -1, w = -1, lru = 0, lrw = 0;
+        uint64_t hsh = 0;   // its sampling hash
         uint32_t types = 0;
         int lu = 0, lw = 0;
         if (q < Q) {
@@ -1161,7 +1174,10 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             }
             bytes += 4;
             bool ok = w != k;
-            if (ok && a.sampled && sample_hash(a.seed, N, k, u, w) >= a.sample_thr) ok = false;
+            if (ok && a.sampled) {
+                hsh = sample_hash(a.seed, N, k, u, w);
+                if (!a.item_thr && hsh >= a.sample_thr) ok = false;
+            }
             if (ok) {
                 const uint32_t iu = a.vinfo[u], iw = a.vinfo[w];
                 lu = (int)(iu >> 26);
@@ -1211,6 +1227,7 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
             // size-3 part (exhaustively true for connected graphs on 4 and 5
             // vertices), so a piece above min(parent \ k) is rejected
             if (N <= 5 && qmin > mu) ok = false;
+            if (ok && a.item_thr && hsh >= a.item_thr[(int64_t)pslot * M + i]) ok = false;
             int got = 0;
             if (ok) {
                 const uint64_t PA = a.padj[pslot];
@@ -1226,12 +1243,20 @@ __global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
                 bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
             }
             if (a.item_children) {   // uniform: every lane is on parent pp
-                const int64_t sg = wave_sum((int64_t)got);
-                if (lane == 0 && sg)
-                    atomicAdd(&a.item_children[(int64_t)pslot * M + i], (unsigned long long)sg);
+                // parents arrive grouped by (parent QP, position): add runs
+                const int64_t item = (int64_t)pslot * M + i;
+                if (item != run_item) {
+                    if (lane == 0 && run_sum)
+                        atomicAdd(&a.item_children[run_item], (unsigned long long)run_sum);
+                    run_item = item;
+                    run_sum = 0;
+                }
+                run_sum += wave_sum((int64_t)got);
             }
         }
     }
+    if (a.item_children && lane == 0 && run_sum)
+        atomicAdd(&a.item_children[run_item], (unsigned long long)run_sum);
     const int64_t te = wave_sum((int64_t)emit);
     const int64_t tc = wave_sum((int64_t)cands);
     const int64_t tb = wave_sum((int64_t)bytes);
@@ -1308,7 +1333,9 @@ struct MergeArgs {
 
 // OR every QP position bitmap into its (pattern, orbit) bitmap.
 __global__ __launch_bounds__(TPB) void k_qp_merge(MergeArgs a) {
-    for (uint64_t it = blockIdx.x; it < a.items; it += gridDim.x) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nw = (uint64_t)gridDim.x * (TPB / 64);
+    for (uint64_t it = (uint64_t)wave_id_global(); it < a.items; it += nw) {
         const uint64_t s = it / a.n;
         const int p = (int)(it - s * a.n);
         const uint64_t v = a.q.kv[2 * s + 1];
@@ -1316,7 +1343,7 @@ __global__ __launch_bounds__(TPB) void k_qp_merge(MergeArgs a) {
         const uint32_t o = (uint32_t)(v >> (3 * p)) & 7u;
         const uint32_t* src = a.qbits + it * a.W;
         uint32_t* dst = a.pbits + ((uint64_t)a.q.pat[s] * a.n + o) * a.W;
-        for (uint32_t w = threadIdx.x; w < a.W; w += TPB) {
+        for (uint32_t w = lane; w < a.W; w += 64) {
             const uint32_t x = src[w];
             if (x && (dst[w] & x) != x) atomicOr(&dst[w], x);
         }
@@ -1336,11 +1363,12 @@ struct MniArgs {
     unsigned out_cap;
 };
 
-// One block per pattern slot: popcount of each orbit bitmap, minimum over
-// orbits (MNI support, Section 2.2).
+// One wavefront per pattern slot: popcount of each orbit bitmap, minimum
+// over orbits (MNI support, Section 2.2).
 __global__ __launch_bounds__(TPB) void k_mni(MniArgs a) {
-    __shared__ unsigned long long part[TPB / 64];
-    for (uint64_t s = blockIdx.x; s < a.slots; s += gridDim.x) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nw = (uint64_t)gridDim.x * (TPB / 64);
+    for (uint64_t s = (uint64_t)wave_id_global(); s < a.slots; s += nw) {
         const uint64_t key = a.c.kv[2 * s];
         if (key == EMPTY_KEY) continue;
         const uint64_t info = a.c.info[s];
@@ -1350,18 +1378,13 @@ __global__ __launch_bounds__(TPB) void k_mni(MniArgs a) {
             for (int cp = 0; cp < a.n; ++cp) {
                 if ((int)((info >> (3 * cp)) & 7u) != cp) continue;
                 const uint32_t* bm = base + (uint64_t)cp * a.pool.W;
-                unsigned long long cnt = 0;
-                for (uint32_t i = threadIdx.x; i < a.pool.W; i += TPB) cnt += __popc(bm[i]);
-                cnt = (unsigned long long)wave_sum((int64_t)cnt);
-                if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
-                __syncthreads();
-                unsigned long long tot = 0;
-                for (int q = 0; q < TPB / 64; ++q) tot += part[q];
-                __syncthreads();
-                if (best < 0 || (int64_t)tot < best) best = (int64_t)tot;
+                int64_t cnt = 0;
+                for (uint32_t i = lane; i < a.pool.W; i += 64) cnt += __popc(bm[i]);
+                cnt = wave_sum(cnt);
+                if (best < 0 || cnt < best) best = cnt;
             }
         }
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             if (best < 0) best = 0;
             a.c.sup[s] = best;
             unsigned idx = atomicAdd(a.out_n, 1u);
@@ -1393,15 +1416,17 @@ __global__ void k_mark_frequent(QPTab q, uint64_t slots, const uint64_t* ckv, co
 // child QP sets are disjoint and sum to the level's QP count.
 
 // Parent embeddings per QP slot and the G_f degree sum of each position.
+// Integer sums keep the features, and so the predictions and the sampling
+// proposal, independent of the order of the atomics.
 __global__ void k_item_stats(const int32_t* par, int64_t rows, int M, const int32_t* frow,
-                             unsigned* cnt, float* degsum) {
+                             unsigned* cnt, unsigned long long* degsum) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int32_t* pr = par + r * (M + 1);
         const int64_t s = pr[M];
         atomicAdd(&cnt[s], 1u);
         for (int i = 0; i < M; ++i)
-            atomicAdd(&degsum[s * M + i], (float)(frow[pr[i] + 1] - frow[pr[i]]));
+            atomicAdd(&degsum[s * M + i], (unsigned long long)(frow[pr[i] + 1] - frow[pr[i]]));
     }
 }
 
@@ -1415,7 +1440,7 @@ struct FeatArgs {
     const int64_t* pos;      // exclusive scan of the item flags
     int32_t* graph;          // rows: graph id of the item (batches)
     const unsigned* cnt;
-    const float* degsum;
+    const unsigned long long* degsum;
     const uint64_t* qadj;    // parent QP tables
     const uint64_t* qlab;
     const int32_t* qpat;
@@ -1444,7 +1469,7 @@ __global__ void k_item_features(FeatArgs a) {
         x[0] = (float)a.n / 8.0f;
         x[1] = (float)(__popcll(a.qadj[s]) / 2) / (float)(npairs > 0 ? npairs : 1);
         x[2] = log1pf((float)c) / 16.0f;
-        x[3] = log1pf(a.degsum[it] / (float)c) / 8.0f;
+        x[3] = log1pf((float)((double)a.degsum[it] / (double)c)) / 8.0f;
         x[4] = log1pf((float)a.csup[a.qpat[s]]) / 16.0f;
         x[5] = log1pf((float)a.tg[L >> 48]) / 16.0f;
         for (int b = 0; b < 2 * FSM_FEATURE_LABELS; ++b) x[6 + b] = 0.0f;
@@ -1464,6 +1489,39 @@ __global__ void k_item_targets(const int32_t* item, int64_t rows,
         const int32_t it = item[r];
         t[2 * r] = log1pf((float)children[it]);
         t[2 * r + 1] = log1pf((float)qps[it]);
+    }
+}
+
+// Predicted children per parent embedding of every item.
+__global__ void k_item_rowcost(const float* y, const int32_t* item, int64_t rows, int M,
+                               const unsigned* cnt, float* rowcost) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t it = item[r];
+        rowcost[it] = expm1f(fmaxf(y[2 * r], 0.0f)) / (float)max(cnt[it / M], 1u);
+    }
+}
+
+// Predicted cost per tile of every key group: the predicted children of its
+// parent embeddings over its tile count.  One wavefront per group.
+__global__ void k_group_cost(const int32_t* gk, const int64_t* goff, const int64_t* gcnt,
+                             const int64_t* tiles, int64_t ngroups, const int32_t* glist,
+                             const int32_t* par, int M, const float* rowcost, float* gcost) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t g = wave_id_global(); g < ngroups; g += nw) {
+        const int32_t k = gk[g];
+        float acc = 0.f;
+        for (int64_t j = lane; j < gcnt[g]; j += 64) {
+            const int32_t* row = par + (int64_t)glist[goff[g] + j] * (M + 1);
+            int i = 0;
+            for (int p = 0; p < M; ++p)
+                if (row[p] == k) i = p;
+            acc += rowcost[(int64_t)row[M] * M + i];
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) gcost[g] = acc / (float)max(tiles[g], (int64_t)1);
     }
 }
 
@@ -1683,6 +1741,7 @@ struct Miner {
     struct ItemRows {
         DBuf<float> x;
         DBuf<int32_t> item, graph;
+        DBuf<unsigned> cnt;   // parent embeddings per parent QP slot
         int64_t rows = 0;
     };
     void item_rows(const Level& P, int n, ItemRows& IR);
@@ -1772,7 +1831,7 @@ struct Miner {
         QPTab q{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
                 L.tab.qcount.p};
         MergeArgs ma{q, pool.p, ppool.p, W, L.n, L.tab.qcap * (uint64_t)L.n};
-        k_qp_merge<<<grid_for((int64_t)ma.items, 1, 1u << 16), TPB, 0, st>>>(ma);
+        k_qp_merge<<<grid_for((int64_t)ma.items, TPB / 64, 1u << 16), TPB, 0, st>>>(ma);
         FSM_LAUNCH_CHECK();
         DBuf<uint64_t> okey(npat ? npat : 1);
         DBuf<int64_t> osup(npat ? npat : 1);
@@ -1780,7 +1839,7 @@ struct Miner {
         on.zero();
         MniArgs m{{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p},
                   {ppool.p, lrank.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
-        k_mni<<<grid_for((int64_t)L.tab.ccap, 1, 1u << 16), TPB, 0, st>>>(m);
+        k_mni<<<grid_for((int64_t)L.tab.ccap, TPB / 64, 1u << 16), TPB, 0, st>>>(m);
         FSM_LAUNCH_CHECK();
         k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(
             q, L.tab.qcap, L.tab.ckv.p, L.tab.csup.p, dtg.p, L.n);
@@ -1821,6 +1880,9 @@ struct Miner {
         int tile_p = TILE_P_MAX;
     };
     void build_groups(const Level& P, int M, int64_t nwork, Groups& G);
+    void order_groups(const Level& P, int M, const ItemRows& IR, const float* y, Groups& G);
+    void proposal_thresholds(const ItemRows& IR, const float* y, int M, int64_t nitems,
+                             DBuf<uint64_t>& thr);
 
     void run();
     void level2();
@@ -1986,11 +2048,108 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G) {
     FSM_HIP(hipStreamSynchronize(st));
 }
 
+// Longest-processing-time order of the key groups for the work queue:
+// groups sorted by predicted cost per tile, largest first, then the tile
+// offsets rebuilt in that order.
+void Miner::order_groups(const Level& P, int M, const ItemRows& IR, const float* y, Groups& G) {
+    const int64_t ng = G.ngroups;
+    if (ng < 2) return;
+    const int64_t nitems = (int64_t)P.tab.qcap * M;
+    DBuf<float> rowcost((size_t)nitems);
+    rowcost.zero();
+    k_item_rowcost<<<grid_for(IR.rows, TPB), TPB, 0, st>>>(y, IR.item.p, IR.rows, M, IR.cnt.p,
+                                                           rowcost.p);
+    FSM_LAUNCH_CHECK();
+    DBuf<int64_t> tiles((size_t)ng);
+    k_key_tiles<<<grid_for(ng, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p, ng, G.tile_p,
+                                                   tiles.p);
+    FSM_LAUNCH_CHECK();
+    DBuf<float> gcost((size_t)ng);
+    k_group_cost<<<grid_for(ng, TPB / 64), TPB, 0, st>>>(G.gk.p, G.goff.p, G.gcnt.p, tiles.p, ng,
+                                                       G.glist.p, P.emb.p, M, rowcost.p, gcost.p);
+    FSM_LAUNCH_CHECK();
+    std::vector<float> hc;
+    std::vector<int32_t> hk;
+    std::vector<int64_t> ho, hn;
+    to_host(hc, gcost.p, (size_t)ng);
+    to_host(hk, G.gk.p, (size_t)ng);
+    to_host(ho, G.goff.p, (size_t)ng);
+    to_host(hn, G.gcnt.p, (size_t)ng);
+    std::vector<int64_t> ord((size_t)ng);
+    for (int64_t g = 0; g < ng; ++g) ord[(size_t)g] = g;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int64_t a, int64_t b) { return hc[(size_t)a] > hc[(size_t)b]; });
+    std::vector<int32_t> pk((size_t)ng);
+    std::vector<int64_t> po((size_t)ng), pn((size_t)ng);
+    for (int64_t g = 0; g < ng; ++g) {
+        pk[(size_t)g] = hk[(size_t)ord[(size_t)g]];
+        po[(size_t)g] = ho[(size_t)ord[(size_t)g]];
+        pn[(size_t)g] = hn[(size_t)ord[(size_t)g]];
+    }
+    to_device(G.gk.p, pk.data(), (size_t)ng);
+    to_device(G.goff.p, po.data(), (size_t)ng);
+    to_device(G.gcnt.p, pn.data(), (size_t)ng);
+    k_key_tiles<<<grid_for(ng, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p, ng, G.tile_p,
+                                                   tiles.p);
+    FSM_LAUNCH_CHECK();
+    const int64_t nt = scan_exclusive(tiles.p, G.toff.p, ng);
+    if (nt != G.ntiles) fail(FSM_EDEVICE, "tile count changed by reordering (%lld vs %lld)",
+                             (long long)nt, (long long)G.ntiles);
+    FSM_HIP(hipMemcpyAsync(G.toff.p + ng, &G.ntiles, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    FSM_HIP(hipStreamSynchronize(st));
+}
+
+// Sampling proposal: keep rate min(1, lambda / sqrt(c_i / e_i)) for work
+// item i, where c_i is its predicted children and e_i its parent
+// embeddings (items whose parents each yield many children are redundant
+// and sampled thinner); lambda makes the expected work sum(rate_i c_i)
+// equal sampling_rate * sum(c_i), the uniform rate's.
+void Miner::proposal_thresholds(const ItemRows& IR, const float* y, int M, int64_t nitems,
+                                DBuf<uint64_t>& thr) {
+    std::vector<float> hy;
+    std::vector<int32_t> hi;
+    std::vector<unsigned> hc;
+    to_host(hy, y, (size_t)(IR.rows * MODEL_OUT));
+    to_host(hi, IR.item.p, (size_t)IR.rows);
+    to_host(hc, IR.cnt.p, IR.cnt.n);
+    const size_t R = (size_t)IR.rows;
+    std::vector<double> c(R), wgt(R);
+    double total = 0.0;
+    for (size_t r = 0; r < R; ++r) {
+        c[r] = std::expm1(std::max(0.0, (double)hy[2 * r]));
+        const double e = std::max(1u, hc[(size_t)hi[r] / (size_t)M]);
+        wgt[r] = 1.0 / std::sqrt(std::max(c[r] / e, 1e-3));
+        total += c[r];
+    }
+    const double budget = opt.sampling_rate * total;
+    auto work = [&](double lam) {
+        double s = 0.0;
+        for (size_t r = 0; r < R; ++r) s += std::min(1.0, lam * wgt[r]) * c[r];
+        return s;
+    };
+    double lo = 0.0, hi_l = 1.0;
+    while (work(hi_l) < budget && hi_l < 1e30) hi_l *= 2.0;
+    for (int it = 0; it < 100; ++it) {
+        const double mid = 0.5 * (lo + hi_l);
+        if (work(mid) < budget) lo = mid; else hi_l = mid;
+    }
+    const double lam = hi_l;
+    const uint64_t uni = (uint64_t)std::ldexp(opt.sampling_rate, 64);
+    std::vector<uint64_t> h((size_t)nitems, uni);
+    for (size_t r = 0; r < R; ++r) {
+        const double rate = std::min(1.0, lam * wgt[r]);
+        h[(size_t)hi[r]] = rate >= 1.0 ? ~0ull : (uint64_t)std::ldexp(rate, 64);
+    }
+    thr.alloc((size_t)nitems);
+    to_device(thr.p, h.data(), h.size());
+}
+
 void Miner::item_rows(const Level& P, int n, ItemRows& IR) {
     const int M = n - 2;
     const int64_t nitems = (int64_t)P.tab.qcap * M;
-    DBuf<unsigned> cnt((size_t)P.tab.qcap);
-    DBuf<float> dsum((size_t)nitems);
+    DBuf<unsigned>& cnt = IR.cnt;
+    cnt.alloc((size_t)P.tab.qcap);
+    DBuf<unsigned long long> dsum((size_t)nitems);
     cnt.zero();
     dsum.zero();
     k_item_stats<<<grid_for(P.rows, TPB), TPB, 0, st>>>(P.emb.p, P.rows, M, frow.p, cnt.p, dsum.p);
@@ -2020,21 +2179,30 @@ void Miner::join(int n) {
     // targets come from the domain pass
     const bool learned = (opt.mode & FSM_LEARNED) && model != nullptr;
     const bool record = opt.record != 0;
+    double pred_raw = 0.0;
     ItemRows IR;
+    DBuf<float> y;
     if ((learned || record) && P.rows > 0) item_rows(P, n, IR);
     if (learned && IR.rows > 0) {
-        DBuf<float> y((size_t)(IR.rows * MODEL_OUT));
+        y.alloc((size_t)(IR.rows * MODEL_OUT));
         model->predict(IR.x.p, IR.rows, y.p);
         DBuf<double> tot(1);
         tot.zero();
         k_pred_total<<<grid_for(IR.rows, TPB, 1024), TPB, 0, st>>>(y.p, IR.rows, 1, tot.p);
         FSM_LAUNCH_CHECK();
-        const double pq = scalar_to_host(tot.p);
+        const double raw = scalar_to_host(tot.p);
+        const double pq = raw * (model->calib[n] > 0 ? model->calib[n] : 1.0);
         L.st.qp_predicted = (int64_t)std::llround(pq);
-        // load <= 1/2, 25% slack; an underestimate still overflows and reruns
-        qhint[n] = pow2_at_least((uint64_t)(2.5 * pq) + 64);
+        // load <= 1/2, 25% slack; an underestimate still overflows and
+        // reruns, an overestimate is capped at 2^26 slots
+        qhint[n] = pow2_at_least((uint64_t)std::min(2.5 * pq + 64, 67108864.0));
+        pred_raw = raw;
     }
     const int64_t nitems = (int64_t)P.tab.qcap * M;
+    // sampled + learned: per-item keep rates from the model (the proposal)
+    DBuf<uint64_t> ithr;
+    if (learned && (opt.mode & FSM_SAMPLED) && IR.rows > 0 && opt.sampling_rate < 1.0)
+        proposal_thresholds(IR, y.p, M, nitems, ithr);
     DBuf<unsigned long long> ich;
     DBuf<unsigned> iqp;
     if (record && IR.rows > 0) {
@@ -2057,7 +2225,7 @@ void Miner::join(int n) {
         a.emitted = counters.p; a.cands = counters.p + 1; a.bytes = counters.p + 3;
         a.prune = opt.disable_pruning ? 0 : 1;
         a.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
-        a.seed = opt.seed; a.sample_thr = thr;
+        a.seed = opt.seed; a.sample_thr = thr; a.item_thr = ithr.p;
         a.counts = counts; a.offsets = offsets; a.out = out; a.out_rows = rows;
         return a;
     };
@@ -2079,6 +2247,7 @@ void Miner::join(int n) {
     };
     Groups G;
     if (nwork > 0) build_groups(P, M, nwork, G);
+    if (y.p && G.ntiles > 0 && opt.schedule == FSM_SCHEDULE_QUEUE) order_groups(P, M, IR, y.p, G);
     const uint32_t dsize = 1u << (n * (n - 1) / 2);
     DBuf<uint16_t> dtab(dsize);
     k_dissect_table<<<grid_for(dsize, TPB), TPB, 0, st>>>(n, dtab.p);
@@ -2098,10 +2267,11 @@ void Miner::join(int n) {
         t.tile_p = G.tile_p;
         t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p; t.flags = R.flags;
         t.item_children = nullptr;
+        t.queue = opt.schedule == FSM_SCHEDULE_STATIC ? 0 : 1;
         t.ctr = counters.p;
         t.prune = opt.disable_pruning ? 0 : 1;
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
-        t.seed = opt.seed; t.sample_thr = thr;
+        t.seed = opt.seed; t.sample_thr = thr; t.item_thr = ithr.p;
         t.dtab = dtab.p;
         return t;
     };
@@ -2141,6 +2311,8 @@ void Miner::join(int n) {
     }
     (void)hipEventDestroy(j0);
     (void)hipEventDestroy(j1);
+    if (pred_raw > 0.0 && L.st.quick_patterns > 0)
+        model->calib[n] = (double)L.st.quick_patterns / pred_raw;
     if (ich.p) {
         DBuf<float> t((size_t)(IR.rows * MODEL_OUT));
         k_item_targets<<<grid_for(IR.rows, TPB), TPB, 0, st>>>(IR.item.p, IR.rows, ich.p, iqp.p,

@@ -19,6 +19,10 @@ struct Model {
     DBuf<float> p, m, v, g;        // float32 master copy, moments, gradient
     DBuf<uint16_t> w;              // bfloat16 working copy
     DBuf<float> scal;              // loss accumulator
+    // per join size: actual / predicted quick patterns of the last level
+    // sized with the current parameters (a summed expm1 of log-space
+    // predictions is biased); 0 = none yet, reset by training
+    mutable double calib[8] = {};
 
     Model(int in_dim, const float* init, uint64_t seed);
     void reset_optimizer();

@@ -237,6 +237,7 @@ float Model::gradient(const float* dx, const float* dt, int64_t rows) {
 // forward pass (before its update).
 float Model::train(const float* dx, const float* dt, int64_t rows, int steps, float lr) {
     hipStream_t st = stream();
+    for (double& c : calib) c = 0.0;   // calibration belongs to the old parameters
     const float beta1 = 0.9f, beta2 = 0.999f;
     for (int k = 0; k < steps; ++k) {
         const bool last = k == steps - 1;

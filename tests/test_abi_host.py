@@ -233,3 +233,14 @@ def test_model_shape_validation():
         assert e.value.code == -1
     text = open(os.path.join(ROOT, "include", "fsm.h")).read()
     assert "#define FSM_FEATURE_LABELS 16" in text and fsm.FEATURES == 6 + 2 * 16
+
+
+def test_score_sampled_host_logic():
+    exact = [(2, (0, 0), 1, 10), (3, (0, 0, 1), 3, 7), (3, (0, 1, 1), 5, 4)]
+    sampled = [(2, (0, 0), 1, 6), (3, (0, 0, 1), 3, 7)]
+    s = fsm.score_sampled(exact, sampled)
+    assert s["found"] == 2 and s["recall"] == pytest.approx(2 / 3) and s["precision"] == 1.0
+    assert s["support_ratio"] == pytest.approx((0.6 + 1.0) / 2) and s["lower_bound"]
+    assert s["by_size"] == {2: 1.0, 3: 0.5}
+    bad = fsm.score_sampled(exact, [(2, (0, 0), 1, 11), (4, (0, 0, 0, 0), 7, 5)])
+    assert not bad["lower_bound"] and bad["precision"] == 0.5
