@@ -9,6 +9,8 @@ subgraphs emitted by all join levels of one step divided by the step's wall
 time.  ``roofline`` covers the dominant kernel (the join level with the
 longest domain pass), timed with HIP events on its launch stream.
 ``cpu_baseline`` is the single-thread CPU oracle on the same workload.
+``batch`` compares plain per-graph calls with batched+learned mining on the
+256-graph workload (same device, identical results required).
 """
 import argparse
 import json
@@ -60,6 +62,63 @@ def profiled_counters(size, workload):
     return vals
 
 
+def batch_comparison(fsm, synth):
+    """The 256-graph workload mined two ways on the same device: plain
+    per-graph fsm_mine calls, and batched+learned (union passes of at most
+    16384 vertices, join tables sized and tiles ordered by a cost model that
+    a warm-up batch trained online).  Both must return identical results."""
+    import torch
+    ws = synth.batch_workload()
+    graphs = [fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"]) for w in ws]
+    sup = [w["support"] for w in ws]
+    smax = ws[0]["max_size"]
+    print(f"[bench] batch workload: {len(ws)} graphs, {sum(w['n'] for w in ws)} vertices",
+          file=sys.stderr, flush=True)
+    fsm.mine(graphs[0], sup[0], smax)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [fsm.mine(g, s, smax) for g, s in zip(graphs, sup)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(f"[bench] plain per-graph: {t_plain:.3f} s", file=sys.stderr, flush=True)
+    model = fsm.Model(fsm.FEATURES, seed=1)
+    mode = fsm.FSM_BATCHED | fsm.FSM_LEARNED
+    t0 = time.perf_counter()
+    fsm.mine_batch(graphs, sup, smax, mode, chunk_vertices=16384, model=model, learn=True,
+                   train_steps=200, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    print(f"[bench] warm-up batch with online training: {t_train:.3f} s", file=sys.stderr,
+          flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fsm.mine_batch(graphs, sup, smax, mode, chunk_vertices=16384, model=model)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[bench] batched+learned: {t_batch:.3f} s", file=sys.stderr, flush=True)
+    same = all(a.patterns == b.patterns for a, b in zip(plain, res))
+    emitted = sum(r.stats["levels"][n]["emitted"] for r in plain
+                  for n in r.stats["levels"] if n >= 4)
+    passes = lambda rs: sum(r.stats["levels"][n]["domain_passes"] for r in rs
+                            for n in r.stats["levels"] if n >= 4)
+    chunks = {}
+    for r in res:
+        chunks.setdefault(r.stats["batch_chunk"], r)
+    model.close()
+    for g in graphs:
+        g.close()
+    return {"workload": "batch256", "graphs": len(ws), "max_size": smax,
+            "patterns": int(sum(len(r) for r in plain)), "embeddings_extended": emitted,
+            "plain_s": round(t_plain, 3), "batched_learned_s": round(t_batch, 3),
+            "speedup": round(t_plain / t_batch, 3),
+            "plain_embeddings_per_s": round(emitted / t_plain, 1),
+            "batched_learned_embeddings_per_s": round(emitted / t_batch, 1),
+            "chunks": len(chunks),
+            "domain_passes_plain": passes(plain),
+            "domain_passes_batched_learned": passes(chunks.values()),
+            "online_training_batch_s": round(t_train, 3),
+            "exact_match_plain": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +126,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl100k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 256-graph plain vs batched+learned comparison")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one elementwise int32 kernel that reads and "
                          "writes this many MiB (calibrates profiler byte counters)")
@@ -134,6 +195,8 @@ def main():
                     "kernel_ms": round(ms, 3), "algorithmic_bytes": nbytes,
                     "valu": valu}
 
+    batch = None if args.no_batch else batch_comparison(fsm, synth)
+
     cpu = None
     exact = None
     if not args.no_cpu_baseline:
@@ -168,6 +231,7 @@ def main():
                    "exact_match_oracle": exact},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

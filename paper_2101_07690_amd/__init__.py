@@ -274,18 +274,23 @@ class Graph:
 
 
 class Result:
-    """Host copy of one mining result: ``patterns`` and ``stats``."""
+    """Host copy of one mining result.  ``sizes``, ``codes`` (rows of the
+    36-byte fsm_code: n, label[7], adj) and ``supports`` are numpy arrays;
+    ``patterns`` is the list of ``(size, labels, adj, support)`` built from
+    them on first use; ``stats`` holds the call's counters."""
 
     def __init__(self, handle):
         L = lib()
         try:
             cnt = L.fsm_result_count(handle)
-            sizes = np.zeros(max(cnt, 1), np.int32)
-            sup = np.zeros(max(cnt, 1), np.int64)
-            codes = (Code * max(cnt, 1))()
+            self.sizes = np.zeros(max(cnt, 1), np.int32)
+            self.supports = np.zeros(max(cnt, 1), np.int64)
+            self.codes = np.zeros((max(cnt, 1), 2 + MAX_SIZE), np.int32)
             _check(L.fsm_result_patterns(
-                handle, None, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), codes,
-                sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+                handle, None, self.sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                self.codes.ctypes.data_as(ctypes.POINTER(Code)),
+                self.supports.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+            self.sizes, self.supports, self.codes = self.sizes[:cnt], self.supports[:cnt], self.codes[:cnt]
             st = Stats()
             _check(L.fsm_result_stats(handle, ctypes.byref(st)))
             nrow = L.fsm_result_training_count(handle)
@@ -299,9 +304,20 @@ class Result:
                     self.train_level.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         finally:
             L.fsm_result_free(handle)
-        self.patterns = [(int(codes[i].n), tuple(int(codes[i].label[j]) for j in range(codes[i].n)),
-                          int(codes[i].adj), int(sup[i])) for i in range(cnt)]
         self.stats = _stats_dict(st)
+        self._patterns = None
+
+    def __len__(self):
+        return len(self.sizes)
+
+    @property
+    def patterns(self):
+        if self._patterns is None:
+            adj = self.codes.view(np.uint32)[:, 1 + MAX_SIZE].tolist()
+            labs = self.codes[:, 1:1 + MAX_SIZE].tolist()
+            self._patterns = [(n, tuple(lab[:n]), a, s) for n, lab, a, s in
+                              zip(self.sizes.tolist(), labs, adj, self.supports.tolist())]
+        return self._patterns
 
 
 def _stats_dict(st):

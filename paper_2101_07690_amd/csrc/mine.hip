@@ -1106,8 +1106,11 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
     return got;
 }
 
+// At most 128 VGPRs (4 waves per SIMD): the occupancy hides the latency of
+// the adjacency probes and bitmap reads better than the extra registers.
 template <int N>
-__global__ __launch_bounds__(TPB) void k_join_tiles(TileArgs a) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles(
+    TileArgs a) {
     constexpr int M = N - 2;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (TPB / 64);
@@ -2194,8 +2197,9 @@ void Miner::join(int n) {
         const double pq = raw * (model->calib[n] > 0 ? model->calib[n] : 1.0);
         L.st.qp_predicted = (int64_t)std::llround(pq);
         // load <= 1/2, 25% slack; an underestimate still overflows and
-        // reruns, an overestimate is capped at 2^26 slots
-        qhint[n] = pow2_at_least((uint64_t)std::min(2.5 * pq + 64, 67108864.0));
+        // reruns, an overestimate is capped at 2^26 slots; a density hint
+        // from earlier chunks of a batch is kept when it is larger
+        qhint[n] = std::max(qhint[n], pow2_at_least((uint64_t)std::min(2.5 * pq + 64, 67108864.0)));
         pred_raw = raw;
     }
     const int64_t nitems = (int64_t)P.tab.qcap * M;
