@@ -64,9 +64,10 @@ def profiled_counters(size, workload):
 
 def batch_comparison(fsm, synth):
     """The 256-graph workload mined two ways on the same device: plain
-    per-graph fsm_mine calls, and batched+learned (union passes of at most
-    16384 vertices, join tables sized and tiles ordered by a cost model that
-    a warm-up batch trained online).  Both must return identical results."""
+    per-graph fsm_mine calls, and batched+learned (union passes with the
+    chunk size and tile height the autotuner picked on a 16-graph sample,
+    join tables sized and tiles ordered by a cost model that a warm-up batch
+    trained online).  Both must return identical results."""
     import torch
     ws = synth.batch_workload()
     graphs = [fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"]) for w in ws]
@@ -81,17 +82,22 @@ def batch_comparison(fsm, synth):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     print(f"[bench] plain per-graph: {t_plain:.3f} s", file=sys.stderr, flush=True)
+    # autotuned shapes: every 16th graph as the sample
+    t0 = time.perf_counter()
+    tuned, cands = fsm.tune_batch(graphs[::16], sup[::16], smax)
+    t_tune = time.perf_counter() - t0
+    print(f"[bench] tuned on {len(graphs[::16])} graphs in {t_tune:.1f} s: {tuned}",
+          file=sys.stderr, flush=True)
     model = fsm.Model(fsm.FEATURES, seed=1)
     mode = fsm.FSM_BATCHED | fsm.FSM_LEARNED
     t0 = time.perf_counter()
-    fsm.mine_batch(graphs, sup, smax, mode, chunk_vertices=16384, model=model, learn=True,
-                   train_steps=200, lr=3e-3)
+    fsm.mine_batch(graphs, sup, smax, mode, model=model, learn=True, train_steps=200, lr=3e-3)
     t_train = time.perf_counter() - t0
     print(f"[bench] warm-up batch with online training: {t_train:.3f} s", file=sys.stderr,
           flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = fsm.mine_batch(graphs, sup, smax, mode, chunk_vertices=16384, model=model)
+    res = fsm.mine_batch(graphs, sup, smax, mode, model=model)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     print(f"[bench] batched+learned: {t_batch:.3f} s", file=sys.stderr, flush=True)
@@ -104,6 +110,7 @@ def batch_comparison(fsm, synth):
     for r in res:
         chunks.setdefault(r.stats["batch_chunk"], r)
     model.close()
+    fsm.reset_tuning()
     for g in graphs:
         g.close()
     return {"workload": "batch256", "graphs": len(ws), "max_size": smax,
@@ -116,6 +123,8 @@ def batch_comparison(fsm, synth):
             "domain_passes_plain": passes(plain),
             "domain_passes_batched_learned": passes(chunks.values()),
             "online_training_batch_s": round(t_train, 3),
+            "tuned": tuned, "tuning_s": round(t_tune, 1),
+            "tuning_candidates_ms": [[c, t, round(ms, 1)] for c, t, ms in cands],
             "exact_match_plain": same}
 
 

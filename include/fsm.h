@@ -155,7 +155,9 @@ typedef struct {
                                       FSM_FEATURES inputs */
     int32_t record;           /* 1: keep one training row per join work item
                                  in the result (fsm_result_training_rows) */
-    int32_t reserved1;
+    int32_t tiles_per_wave;   /* >0: join tiles per wavefront the tile
+                                 height aims for; 0: the tuned value
+                                 (fsm_tune_batch), else 16 */
 } fsm_options;
 
 /* Allocation hooks used for all device memory of later calls (e.g. a
@@ -221,7 +223,7 @@ int fsm_mine_ex(const fsm_graph *g, const fsm_options *opt, fsm_result **out);
  *   mode       FSM_PLAIN or FSM_BATCHED (same meaning here)
  *   outs       receives count result handles; the per-level counters of
  *              every result describe the union pass it was mined in
- * Graphs are mined in chunks of at most 65536 vertices (fsm_mine_batch_ex).
+ * Graphs are mined in chunks (fsm_mine_batch_ex with chunk_vertices 0).
  * Errors: as fsm_mine; FSM_EUNSUPPORTED for more than 2048 graphs or
  * max_size 7 with several graphs.  On failure no handle is returned. */
 int fsm_mine_batch(const fsm_graph *const *graphs, int32_t count,
@@ -234,9 +236,10 @@ typedef struct {
     uint32_t mode;              /* FSM_PLAIN or FSM_BATCHED (same meaning) */
     int64_t chunk_vertices;     /* >0: at most this many vertices in one
                                    union pass (a larger single graph gets a
-                                   pass of its own); 0: 65536 */
+                                   pass of its own); 0: the tuned value
+                                   (fsm_tune_batch), else 16384 */
     int32_t disable_pruning;    /* as fsm_options */
-    int32_t reserved0;
+    int32_t tiles_per_wave;     /* as fsm_options */
     int64_t hash_capacity_min;  /* as fsm_options (first chunk) */
     int64_t pattern_capacity_min;
     struct fsm_model *model;    /* FSM_LEARNED: cost model with FSM_FEATURES
@@ -260,6 +263,30 @@ typedef struct {
 int fsm_mine_batch_ex(const fsm_graph *const *graphs, int32_t count,
                       const int64_t *supports, const fsm_batch_options *opt,
                       fsm_result **outs);
+
+/* Autotuning of the batch shapes.  fsm_tune_batch mines the given graphs
+ * (a representative sample of a workload) once per candidate shape --
+ * chunk_vertices in {8192, 16384, 32768} x tiles_per_wave in {4, 16, 64},
+ * after one warm-up call -- times each call on the host clock, and keeps
+ * the fastest as the library's defaults for later calls that leave
+ * chunk_vertices / tiles_per_wave at 0 (process-wide, until
+ * fsm_reset_tuning).  Results never depend on the shapes. */
+#define FSM_TUNE_MAX 16
+typedef struct {
+    int64_t chunk_vertices;            /* the winner */
+    int32_t tiles_per_wave;
+    int32_t configs;                   /* candidates timed */
+    int64_t cand_chunk[FSM_TUNE_MAX];  /* each candidate and its time */
+    int32_t cand_tiles[FSM_TUNE_MAX];
+    double cand_ms[FSM_TUNE_MAX];
+} fsm_tuning;
+
+/* Errors as fsm_mine_batch; out receives the timings and the winner. */
+int fsm_tune_batch(const fsm_graph *const *graphs, int32_t count, const int64_t *supports,
+                   int32_t max_size, fsm_tuning *out);
+
+/* Forget the tuned defaults (chunk_vertices 16384, tiles_per_wave 16). */
+int fsm_reset_tuning(void);
 
 /* Work-item features of the cost model (one row per join work item: a
  * parent quick pattern P of size n-2 with embeddings, and the position i of

@@ -68,10 +68,19 @@ class Stats(ctypes.Structure):
                 ("reserved0", ctypes.c_int32)]
 
 
+TUNE_MAX = 16
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk_vertices", ctypes.c_int64), ("tiles_per_wave", ctypes.c_int32),
+                ("configs", ctypes.c_int32), ("cand_chunk", ctypes.c_int64 * TUNE_MAX),
+                ("cand_tiles", ctypes.c_int32 * TUNE_MAX), ("cand_ms", ctypes.c_double * TUNE_MAX)]
+
+
 class BatchOptions(ctypes.Structure):
     _fields_ = [("max_size", ctypes.c_int32), ("mode", ctypes.c_uint32),
                 ("chunk_vertices", ctypes.c_int64), ("disable_pruning", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("hash_capacity_min", ctypes.c_int64),
+                ("tiles_per_wave", ctypes.c_int32), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("learn", ctypes.c_int32), ("train_steps", ctypes.c_int32),
                 ("lr", ctypes.c_float), ("reserved1", ctypes.c_int32)]
@@ -83,7 +92,7 @@ class Options(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
-                ("record", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("record", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -134,6 +143,11 @@ def lib():
     L.fsm_mine_batch_ex.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64p,
                                     ctypes.POINTER(BatchOptions), ctypes.POINTER(vp)]
     L.fsm_mine_batch_ex.restype = ctypes.c_int
+    L.fsm_tune_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64p, ctypes.c_int32,
+                                 ctypes.POINTER(Tuning)]
+    L.fsm_tune_batch.restype = ctypes.c_int
+    L.fsm_reset_tuning.argtypes = []
+    L.fsm_reset_tuning.restype = ctypes.c_int
     L.fsm_result_count.argtypes = [vp]
     L.fsm_result_count.restype = ctypes.c_int64
     L.fsm_result_training_count.argtypes = [vp]
@@ -336,7 +350,8 @@ def _stats_dict(st):
 def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
          hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
-         record: bool = False, schedule: int = FSM_SCHEDULE_QUEUE) -> Result:
+         record: bool = False, schedule: int = FSM_SCHEDULE_QUEUE,
+         tiles_per_wave: int = 0) -> Result:
     """Frequent patterns of sizes 2..max_size with MNI support >= support.
     ``model`` (a Model with FEATURES inputs) sizes the join tables when
     ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows."""
@@ -344,6 +359,7 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
     o.model = model.handle.value if model is not None else None
     o.record = 1 if record else 0
     o.schedule = int(schedule)
+    o.tiles_per_wave = int(tiles_per_wave)
     o.support = int(support)
     o.max_size = int(max_size)
     o.mode = int(mode)
@@ -360,7 +376,8 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
 def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
                chunk_vertices: int = 0, disable_pruning: bool = False,
                hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
-               learn: bool = False, train_steps: int = 0, lr: float = 0.0):
+               learn: bool = False, train_steps: int = 0, lr: float = 0.0,
+               tiles_per_wave: int = 0):
     """Mine several graphs in union passes of at most ``chunk_vertices``
     vertices (0: the library default); one Result per graph.  With a
     ``model``, FSM_LEARNED in ``mode`` sizes every chunk's join tables from
@@ -375,6 +392,7 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
     o.max_size = int(max_size)
     o.mode = int(mode)
     o.chunk_vertices = int(chunk_vertices)
+    o.tiles_per_wave = int(tiles_per_wave)
     o.disable_pruning = 1 if disable_pruning else 0
     o.hash_capacity_min = int(hash_capacity_min)
     o.pattern_capacity_min = int(pattern_capacity_min)
@@ -385,6 +403,24 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
     _check(lib().fsm_mine_batch_ex(hs, n, sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    ctypes.byref(o), outs))
     return [Result(ctypes.c_void_p(outs[i])) for i in range(n)]
+
+
+def tune_batch(graphs, supports, max_size: int):
+    """Time the candidate batch shapes on these graphs and keep the fastest
+    as the library's defaults; returns (winner, [(chunk, tiles, ms), ...])."""
+    n = len(graphs)
+    hs = (ctypes.c_void_p * n)(*[g.handle for g in graphs])
+    sup = np.ascontiguousarray(supports, dtype=np.int64)
+    t = Tuning()
+    _check(lib().fsm_tune_batch(hs, n, sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                int(max_size), ctypes.byref(t)))
+    cands = [(int(t.cand_chunk[i]), int(t.cand_tiles[i]), float(t.cand_ms[i]))
+             for i in range(t.configs)]
+    return {"chunk_vertices": int(t.chunk_vertices), "tiles_per_wave": int(t.tiles_per_wave)}, cands
+
+
+def reset_tuning():
+    _check(lib().fsm_reset_tuning())
 
 
 def _f32(a, cols=None):

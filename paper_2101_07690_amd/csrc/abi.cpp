@@ -153,6 +153,8 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
             fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
         if (opt->schedule != FSM_SCHEDULE_QUEUE && opt->schedule != FSM_SCHEDULE_STATIC)
             fail(FSM_EINVAL, "fsm_mine: unknown schedule %d", opt->schedule);
+        if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)
+            fail(FSM_EINVAL, "fsm_mine: tiles_per_wave must be in [0, 4096]");
         if (opt->model && opt->model->m.D != FSM_FEATURES)
             fail(FSM_EINVAL, "fsm_mine: the model must have FSM_FEATURES (%d) inputs", FSM_FEATURES);
         if (opt->model && opt->model->device != g->device)
@@ -202,6 +204,8 @@ int fsm_mine_batch_ex(const fsm_graph* const* graphs, int32_t count, const int64
         if (opt->mode & ~(uint32_t)(FSM_BATCHED | FSM_LEARNED))
             fail(FSM_EINVAL, "fsm_mine_batch: unsupported mode bits 0x%x", opt->mode);
         if (opt->chunk_vertices < 0) fail(FSM_EINVAL, "fsm_mine_batch: chunk_vertices < 0");
+        if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)
+            fail(FSM_EINVAL, "fsm_mine_batch: tiles_per_wave must be in [0, 4096]");
         if (((opt->mode & FSM_LEARNED) || opt->learn) && !opt->model)
             fail(FSM_EINVAL, "fsm_mine_batch: FSM_LEARNED and learn need a model");
         if (opt->model && opt->model->m.D != FSM_FEATURES)
@@ -223,6 +227,27 @@ int fsm_mine_batch_ex(const fsm_graph* const* graphs, int32_t count, const int64
         return rc;
     }
     for (int32_t i = 0; i < count; ++i) outs[i] = rs[(size_t)i];
+    return FSM_OK;
+}
+
+int fsm_tune_batch(const fsm_graph* const* graphs, int32_t count, const int64_t* supports,
+                   int32_t max_size, fsm_tuning* out) {
+    return guarded([&] {
+        if (!graphs || !supports || !out) fail(FSM_EINVAL, "fsm_tune_batch: NULL argument");
+        if (count < 1 || count > 2048) fail(FSM_EINVAL, "fsm_tune_batch: count must be in [1, 2048]");
+        if (max_size < 2 || max_size > 6)
+            fail(FSM_EINVAL, "fsm_tune_batch: max_size must be in [2, 6]");
+        for (int32_t i = 0; i < count; ++i) {
+            if (!graphs[i]) fail(FSM_EINVAL, "fsm_tune_batch: graph %d is NULL", i);
+            if (supports[i] < 1) fail(FSM_EINVAL, "fsm_tune_batch: support %d must be >= 1", i);
+        }
+        tune_batch(graphs, count, supports, max_size, out);
+    });
+}
+
+int fsm_reset_tuning(void) {
+    g_err[0] = '\0';
+    reset_tuning();
     return FSM_OK;
 }
 

@@ -144,4 +144,7 @@ void build_graph(fsm_graph* g, int64_t n, int64_t m, const int32_t* src, const i
 void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r);
 void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
                 const fsm_batch_options& opt, fsm_result* const* rs);
+void tune_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
+                int32_t max_size, fsm_tuning* out);
+void reset_tuning();
 }  // namespace fsm

@@ -26,6 +26,7 @@
 // position), and the MNI support is the smallest orbit popcount.  The QP
 // value word then holds VALID | FREQ | 3-bit orbit slot per position.
 #include <algorithm>
+#include <atomic>
 #include <deque>
 #include <chrono>
 #include <climits>
@@ -1697,6 +1698,13 @@ struct Level {
     fsm_level_stats st{};
 };
 
+// Shapes chosen by fsm_tune_batch, used where a call leaves them at 0.
+struct Tuning {
+    std::atomic<int64_t> chunk_vertices{0};
+    std::atomic<int32_t> tiles_per_wave{0};
+};
+Tuning g_tuning;
+
 uint64_t pow2_at_least(uint64_t x) {
     uint64_t p = 1;
     while (p < x) p <<= 1;
@@ -2038,7 +2046,9 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G) {
                                                     G.goff.p);
     FSM_LAUNCH_CHECK();
     // parents per tile: as many as keep every wave of the grid busy
-    const int64_t want = 16ll * grid_persistent * (TPB / 64);
+    const int32_t tuned = g_tuning.tiles_per_wave.load();
+    const int tpw = opt.tiles_per_wave > 0 ? opt.tiles_per_wave : (tuned > 0 ? tuned : 16);
+    const int64_t want = (int64_t)tpw * grid_persistent * (TPB / 64);
     for (G.tile_p = TILE_P_MAX;; G.tile_p /= 2) {
         k_key_tiles<<<grid_for(G.ngroups, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p,
                                                               G.ngroups, G.tile_p, tiles.p);
@@ -2520,7 +2530,9 @@ int64_t widest_label(const fsm_graph* g) {
 
 void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
                 const fsm_batch_options& bo, fsm_result* const* rs) {
-    const int64_t budget = bo.chunk_vertices > 0 ? bo.chunk_vertices : (int64_t)1 << 16;
+    const int64_t tuned = g_tuning.chunk_vertices.load();
+    const int64_t budget = bo.chunk_vertices > 0 ? bo.chunk_vertices
+                           : (tuned > 0 ? tuned : (int64_t)1 << 14);
     // order by bitmap width (widest first), then pack consecutive graphs
     std::vector<int32_t> ord((size_t)count);
     for (int32_t i = 0; i < count; ++i) ord[(size_t)i] = i;
@@ -2548,6 +2560,7 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
     o.model = bo.model;
     o.record = bo.learn && bo.model ? 1 : 0;
     o.disable_pruning = bo.disable_pruning;
+    o.tiles_per_wave = bo.tiles_per_wave;
     o.sampling_rate = 1.0;
     o.hash_capacity_min = bo.hash_capacity_min;
     o.pattern_capacity_min = bo.pattern_capacity_min;
@@ -2610,6 +2623,53 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
         rs[i]->stats.batch_chunks = chunk;
         rs[i]->stats.batch_splits = splits;
     }
+}
+
+void tune_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
+                int32_t max_size, fsm_tuning* out) {
+    static const int64_t chunks[] = {8192, 16384, 32768};
+    static const int32_t tiles[] = {4, 16, 64};
+    std::vector<fsm_result> rs((size_t)count);
+    std::vector<fsm_result*> rp;
+    for (auto& r : rs) rp.push_back(&r);
+    auto run = [&](int64_t cv, int32_t tpw) {
+        fsm_batch_options bo;
+        memset(&bo, 0, sizeof(bo));
+        bo.max_size = max_size;
+        bo.mode = FSM_BATCHED;
+        bo.chunk_vertices = cv;
+        bo.tiles_per_wave = tpw;
+        for (auto& r : rs) r = fsm_result();
+        FSM_HIP(hipStreamSynchronize(stream()));
+        const auto t0 = std::chrono::steady_clock::now();
+        mine_batch(gs, count, supports, bo, rp.data());
+        FSM_HIP(hipStreamSynchronize(stream()));
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    };
+    run(chunks[1], tiles[1]);   // warm-up: code objects, allocator pools
+    memset(out, 0, sizeof(*out));
+    double best = 0;
+    for (int64_t cv : chunks)
+        for (int32_t tpw : tiles) {
+            const double ms = run(cv, tpw);
+            const int c = out->configs++;
+            out->cand_chunk[c] = cv;
+            out->cand_tiles[c] = tpw;
+            out->cand_ms[c] = ms;
+            if (c == 0 || ms < best) {
+                best = ms;
+                out->chunk_vertices = cv;
+                out->tiles_per_wave = tpw;
+            }
+        }
+    g_tuning.chunk_vertices = out->chunk_vertices;
+    g_tuning.tiles_per_wave = out->tiles_per_wave;
+}
+
+void reset_tuning() {
+    g_tuning.chunk_vertices = 0;
+    g_tuning.tiles_per_wave = 0;
 }
 
 }  // namespace fsm

@@ -186,7 +186,7 @@ def test_ctypes_structs_match_header(tmp_path):
     import subprocess
     structs = {"fsm_code": fsm.Code, "fsm_level_stats": fsm.LevelStats,
                "fsm_stats": fsm.Stats, "fsm_options": fsm.Options,
-               "fsm_batch_options": fsm.BatchOptions}
+               "fsm_batch_options": fsm.BatchOptions, "fsm_tuning": fsm.Tuning}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fsm.h"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -244,3 +244,21 @@ def test_score_sampled_host_logic():
     assert s["by_size"] == {2: 1.0, 3: 0.5}
     bad = fsm.score_sampled(exact, [(2, (0, 0), 1, 11), (4, (0, 0, 0, 0), 7, 5)])
     assert not bad["lower_bound"] and bad["precision"] == 0.5
+
+
+def test_tune_batch_rejects_bad_arguments():
+    import ctypes
+    L = fsm.lib()
+    t = fsm.Tuning()
+    sup = (ctypes.c_int64 * 1)(1)
+    hs = (ctypes.c_void_p * 1)(None)
+    assert L.fsm_tune_batch(hs, 1, sup, 5, None) == -1
+    assert L.fsm_tune_batch(hs, 1, sup, 7, ctypes.byref(t)) == -1
+    assert L.fsm_tune_batch(hs, 1, sup, 5, ctypes.byref(t)) == -1   # NULL graph
+    assert L.fsm_tune_batch(hs, 0, sup, 5, ctypes.byref(t)) == -1
+    assert L.fsm_reset_tuning() == 0
+    o = fsm.BatchOptions()
+    o.max_size, o.tiles_per_wave = 4, -1
+    outs = (ctypes.c_void_p * 1)()
+    assert L.fsm_mine_batch_ex(hs, 1, sup, ctypes.byref(o), outs) == -1
+    assert b"tiles_per_wave" in L.fsm_last_error()

@@ -80,3 +80,22 @@ def test_batch_rejects_size7_for_several_graphs():
     finally:
         g1.close()
         g2.close()
+
+
+def test_tune_batch_picks_a_candidate_and_keeps_results():
+    ws = [w for w in synth.batch_workload() if w["n"] < 2500][:8]
+    gs = [build(w["src"], w["dst"], w["vertex_labels"]) for w in ws]
+    sup = [w["support"] for w in ws]
+    try:
+        print("tune", len(ws), "graphs", flush=True)
+        best, cands = fsm.tune_batch(gs, sup, 4)
+        assert len(cands) == 9
+        assert (best["chunk_vertices"], best["tiles_per_wave"]) in [(c, t) for c, t, _ in cands]
+        assert min(cands, key=lambda c: c[2])[:2] == (best["chunk_vertices"], best["tiles_per_wave"])
+        tuned = fsm.mine_batch(gs, sup, 4)
+        for g, s, r in zip(gs, sup, tuned):
+            assert r.patterns == fsm.mine(g, s, 4).patterns
+    finally:
+        fsm.reset_tuning()
+        for g in gs:
+            g.close()
