@@ -169,6 +169,22 @@ __device__ __forceinline__ int64_t qp_slot(const Rec& R, uint64_t key, uint64_t 
     return -1;
 }
 
+// Size 5: the parent's own triple {k, b1, b2} is connected and leaves the
+// connected piece {k, u, w} when k is shared, so it is a valid split of the
+// child; the accepted split is the lexicographically smallest, hence a child
+// can only be kept when sorted(k, u, w) < sorted(parent) (exact filter).
+__device__ __forceinline__ void sort3(int32_t a, int32_t b, int32_t c, int32_t& x, int32_t& y,
+                                      int32_t& z) {
+    x = min(a, min(b, c));
+    z = max(a, max(b, c));
+    y = a ^ b ^ c ^ x ^ z;
+}
+
+__device__ __forceinline__ bool lex_less3(int32_t a0, int32_t a1, int32_t a2, int32_t b0,
+                                          int32_t b1, int32_t b2) {
+    return a0 < b0 || (a0 == b0 && (a1 < b1 || (a1 == b1 && a2 < b2)));
+}
+
 // bit r of the bitmap at `bm`: read first, atomicOr only when unset
 __device__ __forceinline__ void set_bit(uint32_t* bm, int32_t r) {
     uint32_t* w = bm + (r >> 5);
@@ -723,11 +739,18 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                     bool ok = w != k;
 #pragma unroll
                     for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
-                    // n <= 5: the smallest vertex of every child lies in the
+                    // n = 4: the smallest vertex of every child lies in the
                     // accepted size-3 part (checked exhaustively for all
-                    // connected graphs on 4 and 5 vertices), so a piece whose
-                    // three vertices all exceed min(parent \ k) is rejected
-                    if (N <= 5 && ok && min(k, min(u, w)) > mu) ok = false;
+                    // connected graphs on 4 vertices), so a piece whose three
+                    // vertices all exceed min(parent \ k) is rejected; n = 5:
+                    // the piece must precede the parent's triple (lex_less3)
+                    if (N == 4 && ok && min(k, min(u, w)) > mu) ok = false;
+                    if (N == 5 && ok) {
+                        int32_t q0, q1, q2, p0, p1, p2;
+                        sort3(k, u, w, q0, q1, q2);
+                        sort3(cv[0], cv[1 % M], cv[2 % M], p0, p1, p2);
+                        if (!lex_less3(q0, q1, q2, p0, p1, p2)) ok = false;
+                    }
                     if (ok && a.sampled && sample_hash(a.seed, N, k, u, w) >= sthr) ok = false;
                     if (ok) {
                         const int lu = a.vf[u], lw = a.vf[w];
@@ -1200,6 +1223,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             }
         }
         const int32_t qmin = min(k, min(u, w));
+        int32_t q0 = 0, q1 = 0, q2 = 0;
+        if (N == 5) sort3(k, u, w, q0, q1, q2);
         const int32_t pb = (int32_t)(a.goff[g] + pt * a.tile_p);
         const int32_t pe = (int32_t)min(a.goff[g] + a.gcnt[g], (int64_t)pb + a.tile_p);
         if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
@@ -1227,10 +1252,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             bool ok = types != 0;
 #pragma unroll
             for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
-            // n <= 5: the smallest vertex of every child lies in the accepted
-            // size-3 part (exhaustively true for connected graphs on 4 and 5
-            // vertices), so a piece above min(parent \ k) is rejected
-            if (N <= 5 && qmin > mu) ok = false;
+            // n = 4: the smallest vertex of every child lies in the accepted
+            // size-3 part (exhaustively true for connected graphs on 4
+            // vertices), so a piece above min(parent \ k) is rejected; n = 5:
+            // the piece must precede the parent's triple (lex_less3)
+            if (N == 4 && qmin > mu) ok = false;
+            if (N == 5) {
+                int32_t p0, p1, p2;
+                sort3(cv[0], cv[1 % M], cv[2 % M], p0, p1, p2);
+                if (!lex_less3(q0, q1, q2, p0, p1, p2)) ok = false;
+            }
             if (ok && a.item_thr && hsh >= a.item_thr[(int64_t)pslot * M + i]) ok = false;
             int got = 0;
             if (ok) {

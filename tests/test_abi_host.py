@@ -262,3 +262,30 @@ def test_tune_batch_rejects_bad_arguments():
     outs = (ctypes.c_void_p * 1)()
     assert L.fsm_mine_batch_ex(hs, 1, sup, ctypes.byref(o), outs) == -1
     assert b"tiles_per_wave" in L.fsm_last_error()
+
+
+def test_size5_parent_triple_bounds_the_accepted_piece():
+    # For a size-5 child joined from a connected size-3 parent {k, b1, b2}
+    # and a connected piece {k, u, w}, the parent's triple is itself a valid
+    # split (v' = k), so whenever the rule accepts {k, u, w} its sorted ids
+    # are lexicographically smaller than the parent's.  Checked for every
+    # connected graph on 5 vertices, every such split, three id assignments.
+    rng = np.random.default_rng(55)
+    pairs = list(itertools.combinations(range(5), 2))
+    checked = 0
+    for mask in range(1, 1 << 10):
+        edges = [pairs[k] for k in range(10) if mask >> k & 1]
+        if not connected(range(5), edges):
+            continue
+        for _ in range(3):
+            ids = [int(x) for x in rng.permutation(50)[:5]]
+            lm, sh = fsm.dissect(ids, adj_bits(5, edges))
+            piece = [p for p in range(5) if lm >> p & 1]
+            rest = [p for p in range(5) if not lm >> p & 1]
+            parent = rest + [sh]
+            sub = lambda vs: [e for e in edges if e[0] in vs and e[1] in vs]
+            assert connected(piece, sub(piece)) and connected(parent, sub(parent))
+            key = lambda vs: sorted(ids[p] for p in vs)
+            assert key(piece) < key(parent), (ids, edges)
+            checked += 1
+    assert checked == 728 * 3
