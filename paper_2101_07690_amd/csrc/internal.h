@@ -105,6 +105,10 @@ void to_device(T* d, const T* h, size_t count) {
 // Exclusive prefix sum of n int64 values (in == out allowed); returns the total.
 int64_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n);
 
+// Sort (key, value) pairs by key within every segment [off[s], off[s+1]).
+void sort_segments(const uint64_t* keys_in, uint64_t* keys_out, const uint8_t* vals_in,
+                   uint8_t* vals_out, int items, int segments, const int32_t* off);
+
 inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;

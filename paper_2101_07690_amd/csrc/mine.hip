@@ -470,6 +470,51 @@ __device__ __forceinline__ void decode_pair(int64_t r, int32_t* a, int32_t* b) {
     *a = (int32_t)(r - bb * (bb - 1) / 2);
 }
 
+// Piece q of joining vertex k (rk = row[k], dk = deg(k), ncen = C(dk,2)):
+// the k-centre pairs {u < w} of N(k) first, then the k-leaf paths k-u-w
+// (w in N(u)); returns true for a k-centre piece.
+__device__ __forceinline__ bool piece_at(const int32_t* row, const int32_t* col,
+                                         const int32_t* leafoff, int32_t rk, int32_t dk,
+                                         int64_t ncen, int64_t q, int32_t& u, int32_t& w) {
+    if (q < ncen) {
+        int32_t ia, ib;
+        decode_pair(q, &ia, &ib);
+        u = col[rk + ia];
+        w = col[rk + ib];
+        return true;
+    }
+    const int32_t rr = (int32_t)(q - ncen);
+    int32_t lo = 0, hi = dk - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (leafoff[rk + mid] <= rr) lo = mid; else hi = mid - 1;
+    }
+    u = col[rk + lo];
+    w = col[row[u] + (rr - leafoff[rk + lo])];
+    return false;
+}
+
+// Size-5 piece lists: every vertex's pieces as key (min(u,w) << 32 |
+// max(u,w)) and code (bit 0: k-leaf, bit 1: u is the larger id), at
+// poff[k] + q; one wavefront per vertex.  Sorted by key afterwards.
+__global__ void k_piece_fill(const int32_t* row, const int32_t* col, const int32_t* leafoff,
+                             const int64_t* npieces, const int64_t* poff, int64_t n,
+                             uint64_t* key, uint8_t* code) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t k = wave_id_global(); k < n; k += nw) {
+        const int32_t rk = row[k], dk = row[k + 1] - rk;
+        const int64_t ncen = (int64_t)dk * (dk - 1) / 2, Q = npieces[k];
+        for (int64_t q = lane; q < Q; q += 64) {
+            int32_t u, w;
+            const bool centre = piece_at(row, col, leafoff, rk, dk, ncen, q, u, w);
+            const int32_t lo = min(u, w), hi = max(u, w);
+            key[poff[k] + q] = (uint64_t)(uint32_t)lo << 32 | (uint32_t)hi;
+            code[poff[k] + q] = (uint8_t)((centre ? 0u : 1u) | (u > w ? 2u : 0u));
+        }
+    }
+}
+
 // One wave per centre c; lanes over neighbour pairs u < w.  Each pair is a
 // wedge (c; u, w) stored (c, u, w); when c < u and u ~ w it is also the
 // triangle stored (c, u, w) (each triangle once, at its smallest vertex).
@@ -944,6 +989,9 @@ struct TileArgs {
     const Rec* rec;          // QP table (insert path)
     const uint32_t* flags;   // overflow / error bits of the pass
     unsigned long long* item_children;   // when recording: children per work item
+    const uint64_t* pkey;    // size 5: sorted piece lists (null: decode pieces)
+    const uint8_t* pcode;
+    const int64_t* poff;
     int queue;               // 1: waves take tiles from a device counter (ctr[2]);
                              // 0: wave w takes tiles w, w + waves, ...
     unsigned long long* ctr; // [emitted, candidates, -, bytes]
@@ -1182,22 +1230,19 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         uint64_t hsh = 0;   // its sampling hash
         uint32_t types = 0;
         int lu = 0, lw = 0;
+        uint64_t lkey = ~0ull;   // sorted lists: this lane's (min, max) key
         if (q < Q) {
-            const bool centre = q < ncen;
-            if (centre) {
-                int32_t ia, ib;
-                decode_pair(q, &ia, &ib);
-                u = a.col[rk + ia];
-                w = a.col[rk + ib];
+            bool centre;
+            if (N == 5 && a.pkey) {
+                const int64_t x = a.poff[k] + q;
+                lkey = a.pkey[x];
+                const uint32_t cd = a.pcode[x];
+                const int32_t lo = (int32_t)(lkey >> 32), hi = (int32_t)(lkey & 0xffffffffu);
+                centre = !(cd & 1u);
+                u = (cd & 2u) ? hi : lo;
+                w = (cd & 2u) ? lo : hi;
             } else {
-                const int32_t rr = (int32_t)(q - ncen);
-                int32_t lo = 0, hi = dk - 1;
-                while (lo < hi) {
-                    int32_t mid = (lo + hi + 1) >> 1;
-                    if (a.leafoff[rk + mid] <= rr) lo = mid; else hi = mid - 1;
-                }
-                u = a.col[rk + lo];
-                w = a.col[a.row[u] + (rr - a.leafoff[rk + lo])];
+                centre = piece_at(a.row, a.col, a.leafoff, rk, dk, ncen, q, u, w);
             }
             bytes += 4;
             bool ok = w != k;
@@ -1224,7 +1269,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
         const int32_t qmin = min(k, min(u, w));
         int32_t q0 = 0, q1 = 0, q2 = 0;
-        if (N == 5) sort3(k, u, w, q0, q1, q2);
+        if (N == 5 && !a.pkey) sort3(k, u, w, q0, q1, q2);
+        // sorted lists: the tile's smallest key (every lane's key is >= it)
+        const uint64_t tkey = (N == 5 && a.pkey) ? a.pkey[a.poff[k] + qt * 64] : 0;
         const int32_t pb = (int32_t)(a.goff[g] + pt * a.tile_p);
         const int32_t pe = (int32_t)min(a.goff[g] + a.gcnt[g], (int64_t)pb + a.tile_p);
         if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
@@ -1248,6 +1295,13 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 if (j != i) mu = min(mu, cv[j]);
             }
             if (lane == 0) bytes += 4ull * (M + 1);
+            uint64_t pkey = 0;   // size 5: key of the parent's other two vertices
+            if (N == 5) {
+                const int32_t b1 = cv[i == 0 ? 1 : 0], b2 = cv[i == 2 ? 1 : 2 % M];
+                pkey = (uint64_t)(uint32_t)min(b1, b2) << 32 | (uint32_t)max(b1, b2);
+                // no piece of this tile precedes the parent's triple
+                if (a.pkey && tkey >= pkey) continue;
+            }
             const int32_t pslot = prow[M];
             bool ok = types != 0;
 #pragma unroll
@@ -1258,9 +1312,15 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             // the piece must precede the parent's triple (lex_less3)
             if (N == 4 && qmin > mu) ok = false;
             if (N == 5) {
-                int32_t p0, p1, p2;
-                sort3(cv[0], cv[1 % M], cv[2 % M], p0, p1, p2);
-                if (!lex_less3(q0, q1, q2, p0, p1, p2)) ok = false;
+                // for a fixed k, sorted triples containing k order as the
+                // (min, max) pairs of their other two vertices
+                if (a.pkey) {
+                    if (lkey >= pkey) ok = false;
+                } else {
+                    int32_t p0, p1, p2;
+                    sort3(cv[0], cv[1 % M], cv[2 % M], p0, p1, p2);
+                    if (!lex_less3(q0, q1, q2, p0, p1, p2)) ok = false;
+                }
             }
             if (ok && a.item_thr && hsh >= a.item_thr[(int64_t)pslot * M + i]) ok = false;
             int got = 0;
@@ -1589,6 +1649,12 @@ __global__ void k_union_graph(const int32_t* row, const int32_t* col, const int3
         }
         if (x < nnz) ucol[eoff + x] = (int32_t)(col[x] + voff);
     }
+}
+
+__global__ void k_offsets32(const int64_t* in, int64_t n, int32_t* out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)in[i];
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -1922,6 +1988,7 @@ struct Miner {
         int tile_p = TILE_P_MAX;
     };
     void build_groups(const Level& P, int M, int64_t nwork, Groups& G);
+    void sorted_pieces(DBuf<int64_t>& poff, DBuf<uint64_t>& key, DBuf<uint8_t>& code);
     void order_groups(const Level& P, int M, const ItemRows& IR, const float* y, Groups& G);
     void proposal_thresholds(const ItemRows& IR, const float* y, int M, int64_t nitems,
                              DBuf<uint64_t>& thr);
@@ -2188,6 +2255,30 @@ void Miner::proposal_thresholds(const ItemRows& IR, const float* y, int M, int64
     to_device(thr.p, h.data(), h.size());
 }
 
+// Piece lists of G_f sorted by key within every joining vertex; left empty
+// (the join then decodes pieces) when there are 2^31 pieces or more.
+void Miner::sorted_pieces(DBuf<int64_t>& poff, DBuf<uint64_t>& key, DBuf<uint8_t>& code) {
+    const int64_t n = g->n;
+    poff.alloc((size_t)n + 1);
+    const int64_t total = scan_exclusive(npieces.p, poff.p, n);
+    if (total <= 0 || total >= (int64_t)INT32_MAX) {
+        poff.reset();
+        return;
+    }
+    FSM_HIP(hipMemcpyAsync(poff.p + n, &total, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    DBuf<uint64_t> k0((size_t)total);
+    DBuf<uint8_t> c0((size_t)total);
+    k_piece_fill<<<grid_for(n, TPB / 64), TPB, 0, st>>>(frow.p, fcol.p, leafoff.p, npieces.p,
+                                                        poff.p, n, k0.p, c0.p);
+    FSM_LAUNCH_CHECK();
+    DBuf<int32_t> off32((size_t)n + 1);
+    k_offsets32<<<grid_for(n + 1, TPB), TPB, 0, st>>>(poff.p, n + 1, off32.p);
+    FSM_LAUNCH_CHECK();
+    key.alloc((size_t)total);
+    code.alloc((size_t)total);
+    sort_segments(k0.p, key.p, c0.p, code.p, (int)total, (int)n, off32.p);
+}
+
 void Miner::item_rows(const Level& P, int n, ItemRows& IR) {
     const int M = n - 2;
     const int64_t nitems = (int64_t)P.tab.qcap * M;
@@ -2293,6 +2384,12 @@ void Miner::join(int n) {
     Groups G;
     if (nwork > 0) build_groups(P, M, nwork, G);
     if (y.p && G.ntiles > 0 && opt.schedule == FSM_SCHEDULE_QUEUE) order_groups(P, M, IR, y.p, G);
+    // size 5: pieces of every joining vertex sorted by their (min, max) key,
+    // so that the pieces preceding a parent's triple are a prefix of a tile
+    DBuf<int64_t> poff;
+    DBuf<uint64_t> pkey;
+    DBuf<uint8_t> pcode;
+    if (n == 5 && G.ntiles > 0) sorted_pieces(poff, pkey, pcode);
     const uint32_t dsize = 1u << (n * (n - 1) / 2);
     DBuf<uint16_t> dtab(dsize);
     k_dissect_table<<<grid_for(dsize, TPB), TPB, 0, st>>>(n, dtab.p);
@@ -2312,6 +2409,9 @@ void Miner::join(int n) {
         t.tile_p = G.tile_p;
         t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p; t.flags = R.flags;
         t.item_children = nullptr;
+        t.pkey = pkey.p;
+        t.pcode = pcode.p;
+        t.poff = poff.p;
         t.queue = opt.schedule == FSM_SCHEDULE_STATIC ? 0 : 1;
         t.ctr = counters.p;
         t.prune = opt.disable_pruning ? 0 : 1;
