@@ -267,7 +267,8 @@ int fsm_mine_batch_ex(const fsm_graph *const *graphs, int32_t count,
 /* Autotuning of the batch shapes.  fsm_tune_batch mines the given graphs
  * (a representative sample of a workload) once per candidate shape --
  * chunk_vertices in {8192, 16384, 32768} x tiles_per_wave in {4, 16, 64},
- * after one warm-up call -- times each call on the host clock, and keeps
+ * after one warm-up call -- times each twice on the host clock (the faster
+ * of the two counts), and keeps
  * the fastest as the library's defaults for later calls that leave
  * chunk_vertices / tiles_per_wave at 0 (process-wide, until
  * fsm_reset_tuning).  Results never depend on the shapes. */

@@ -247,7 +247,7 @@ int fsm_tune_batch(const fsm_graph* const* graphs, int32_t count, const int64_t*
 
 int fsm_reset_tuning(void) {
     g_err[0] = '\0';
-    reset_tuning();
+    set_tuning(0, 0);
     return FSM_OK;
 }
 

@@ -148,7 +148,9 @@ void build_graph(fsm_graph* g, int64_t n, int64_t m, const int32_t* src, const i
 void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r);
 void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
                 const fsm_batch_options& opt, fsm_result* const* rs);
+// Shapes used where a call leaves chunk_vertices / tiles_per_wave at 0
+// (0: the built-in defaults).
+void set_tuning(int64_t chunk_vertices, int32_t tiles_per_wave);
 void tune_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
                 int32_t max_size, fsm_tuning* out);
-void reset_tuning();
 }  // namespace fsm
