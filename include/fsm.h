@@ -265,13 +265,13 @@ int fsm_mine_batch_ex(const fsm_graph *const *graphs, int32_t count,
                       fsm_result **outs);
 
 /* Autotuning of the batch shapes.  fsm_tune_batch mines the given graphs
- * (a representative sample of a workload) once per candidate shape --
+ * (a representative sample of a workload) twice per candidate shape --
  * chunk_vertices in {8192, 16384, 32768} x tiles_per_wave in {4, 16, 64},
- * after one warm-up call -- times each twice on the host clock (the faster
- * of the two counts), and keeps
- * the fastest as the library's defaults for later calls that leave
- * chunk_vertices / tiles_per_wave at 0 (process-wide, until
- * fsm_reset_tuning).  Results never depend on the shapes. */
+ * after one warm-up call -- times each call on the host clock, scores a
+ * candidate by its faster call, and keeps the fastest candidate as the
+ * library's defaults for later calls that leave chunk_vertices /
+ * tiles_per_wave at 0 (process-wide, until fsm_reset_tuning).  Results
+ * never depend on the shapes. */
 #define FSM_TUNE_MAX 16
 typedef struct {
     int64_t chunk_vertices;            /* the winner */
