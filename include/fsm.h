@@ -116,6 +116,9 @@ typedef struct {
     int64_t qp_capacity;      /* quick-pattern table slots of the last pass */
     int64_t qp_predicted;     /* FSM_LEARNED join levels: the cost model's
                                  estimate of quick_patterns (0 otherwise) */
+    int64_t rank_slices;      /* domain passes over vertex-rank slices: 1
+                                 when the domain bitmaps of the level fit
+                                 the pool budget at once */
 } fsm_level_stats;
 
 typedef struct {
@@ -158,6 +161,10 @@ typedef struct {
     int32_t tiles_per_wave;   /* >0: join tiles per wavefront the tile
                                  height aims for; 0: the tuned value
                                  (fsm_tune_batch), else 16 */
+    int64_t pool_budget_mib;  /* >0: device memory for the domain bitmaps of
+                                 a level, in MiB; 0: 40% of the free memory.
+                                 Bitmaps larger than this are computed in
+                                 vertex-rank slices, one join pass each */
 } fsm_options;
 
 /* Allocation hooks used for all device memory of later calls (e.g. a
@@ -251,6 +258,7 @@ typedef struct {
     int32_t train_steps;
     float lr;
     int32_t reserved1;
+    int64_t pool_budget_mib;    /* as fsm_options */
 } fsm_batch_options;
 
 /* fsm_mine_batch with options.  Graphs are ordered by their most populous

@@ -54,7 +54,7 @@ class LevelStats(ctypes.Structure):
                 ("algorithmic_bytes", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
                 ("domain_passes", ctypes.c_int64), ("qp_capacity", ctypes.c_int64),
-                ("qp_predicted", ctypes.c_int64)]
+                ("qp_predicted", ctypes.c_int64), ("rank_slices", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -83,7 +83,8 @@ class BatchOptions(ctypes.Structure):
                 ("tiles_per_wave", ctypes.c_int32), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("learn", ctypes.c_int32), ("train_steps", ctypes.c_int32),
-                ("lr", ctypes.c_float), ("reserved1", ctypes.c_int32)]
+                ("lr", ctypes.c_float), ("reserved1", ctypes.c_int32),
+                ("pool_budget_mib", ctypes.c_int64)]
 
 
 class Options(ctypes.Structure):
@@ -92,7 +93,8 @@ class Options(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("sampling_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
-                ("record", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32)]
+                ("record", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
+                ("pool_budget_mib", ctypes.c_int64)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -351,7 +353,7 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
          hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
          record: bool = False, schedule: int = FSM_SCHEDULE_QUEUE,
-         tiles_per_wave: int = 0) -> Result:
+         tiles_per_wave: int = 0, pool_budget_mib: int = 0) -> Result:
     """Frequent patterns of sizes 2..max_size with MNI support >= support.
     ``model`` (a Model with FEATURES inputs) sizes the join tables when
     ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows."""
@@ -360,6 +362,7 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
     o.record = 1 if record else 0
     o.schedule = int(schedule)
     o.tiles_per_wave = int(tiles_per_wave)
+    o.pool_budget_mib = int(pool_budget_mib)
     o.support = int(support)
     o.max_size = int(max_size)
     o.mode = int(mode)
@@ -377,7 +380,7 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
                chunk_vertices: int = 0, disable_pruning: bool = False,
                hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
                learn: bool = False, train_steps: int = 0, lr: float = 0.0,
-               tiles_per_wave: int = 0):
+               tiles_per_wave: int = 0, pool_budget_mib: int = 0):
     """Mine several graphs in union passes of at most ``chunk_vertices``
     vertices (0: the library default); one Result per graph.  With a
     ``model``, FSM_LEARNED in ``mode`` sizes every chunk's join tables from
@@ -393,6 +396,7 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
     o.mode = int(mode)
     o.chunk_vertices = int(chunk_vertices)
     o.tiles_per_wave = int(tiles_per_wave)
+    o.pool_budget_mib = int(pool_budget_mib)
     o.disable_pruning = 1 if disable_pruning else 0
     o.hash_capacity_min = int(hash_capacity_min)
     o.pattern_capacity_min = int(pattern_capacity_min)

@@ -155,6 +155,7 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
             fail(FSM_EINVAL, "fsm_mine: unknown schedule %d", opt->schedule);
         if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)
             fail(FSM_EINVAL, "fsm_mine: tiles_per_wave must be in [0, 4096]");
+        if (opt->pool_budget_mib < 0) fail(FSM_EINVAL, "fsm_mine: pool_budget_mib < 0");
         if (opt->model && opt->model->m.D != FSM_FEATURES)
             fail(FSM_EINVAL, "fsm_mine: the model must have FSM_FEATURES (%d) inputs", FSM_FEATURES);
         if (opt->model && opt->model->device != g->device)
@@ -206,6 +207,7 @@ int fsm_mine_batch_ex(const fsm_graph* const* graphs, int32_t count, const int64
         if (opt->chunk_vertices < 0) fail(FSM_EINVAL, "fsm_mine_batch: chunk_vertices < 0");
         if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)
             fail(FSM_EINVAL, "fsm_mine_batch: tiles_per_wave must be in [0, 4096]");
+        if (opt->pool_budget_mib < 0) fail(FSM_EINVAL, "fsm_mine_batch: pool_budget_mib < 0");
         if (((opt->mode & FSM_LEARNED) || opt->learn) && !opt->model)
             fail(FSM_EINVAL, "fsm_mine_batch: FSM_LEARNED and learn need a model");
         if (opt->model && opt->model->m.D != FSM_FEATURES)

@@ -70,7 +70,8 @@ struct CodeTab {
 struct Pool {
     uint32_t* words;           // table slot s owns bitmaps s*n .. s*n+n-1
     const int32_t* lrank;      // rank of each vertex among its label's vertices
-    uint32_t W;                // words per bitmap
+    uint32_t W;                // words per bitmap in this pass
+    int32_t rbase;             // this pass covers ranks rbase .. rbase + 32 W - 1
 };
 
 struct Rec {
@@ -192,6 +193,13 @@ __device__ __forceinline__ void set_bit(uint32_t* bm, int32_t r) {
     if (!(*w & bit)) atomicOr(w, bit);
 }
 
+// Domain passes cover the ranks in slices: rank r is set when it falls in
+// [rbase, rbase + 32 W).
+__device__ __forceinline__ void set_bit_in(uint32_t* bm, int32_t r, int32_t rbase, uint32_t W) {
+    const uint32_t x = (uint32_t)(r - rbase);
+    if (x < 32u * W) set_bit(bm, (int32_t)x);
+}
+
 // Domain pass: record one subgraph; returns its QP slot (or -1).
 template <int N>
 __device__ __forceinline__ int64_t record(const Rec& R, uint64_t key, uint64_t L, uint64_t A,
@@ -200,7 +208,8 @@ __device__ __forceinline__ int64_t record(const Rec& R, uint64_t key, uint64_t L
     if (s < 0) return -1;
     uint32_t* base = R.pool.words + (uint64_t)s * N * R.pool.W;
 #pragma unroll
-    for (int p = 0; p < N; ++p) set_bit(base + (uint64_t)p * R.pool.W, R.pool.lrank[v[p]]);
+    for (int p = 0; p < N; ++p)
+        set_bit_in(base + (uint64_t)p * R.pool.W, R.pool.lrank[v[p]], R.pool.rbase, R.pool.W);
     return s;
 }
 
@@ -985,6 +994,7 @@ struct TileArgs {
     const uint16_t* dtab;    // dissection table of this size
     uint32_t* bits;          // QP-position bitmaps
     uint32_t W;
+    int32_t rbase;           // first rank of this pass's slice
     int prune;
     const Rec* rec;          // QP table (insert path)
     const uint32_t* flags;   // overflow / error bits of the pass
@@ -1158,7 +1168,7 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
 #pragma unroll
                         for (int p = 0; p < N; ++p) {
                             if (p < M && p != i) continue;
-                            set_bit(base + (uint64_t)p * W, lr[p]);
+                            set_bit_in(base + (uint64_t)p * W, lr[p], a.rbase, W);
                         }
                         c.b1 = c.b0;
                         c.b0 = (uint64_t)s + 1;
@@ -1166,7 +1176,7 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
 #pragma unroll
                     for (int p = 0; p < M; ++p) {
                         if (p == i) continue;
-                        set_bit(base + (uint64_t)p * W, lr[p]);
+                        set_bit_in(base + (uint64_t)p * W, lr[p], a.rbase, W);
                     }
                 }
                 ++got;
@@ -1458,36 +1468,65 @@ struct MniArgs {
     unsigned out_cap;
 };
 
-// One wavefront per pattern slot: popcount of each orbit bitmap, minimum
-// over orbits (MNI support, Section 2.2).
-__global__ __launch_bounds__(TPB) void k_mni(MniArgs a) {
+// One wavefront per pattern slot: add the popcount of each orbit bitmap
+// of this pass's rank slice to the orbit's domain size.
+__global__ __launch_bounds__(TPB) void k_orbit_count(MniArgs a, int64_t* ocnt) {
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t nw = (uint64_t)gridDim.x * (TPB / 64);
     for (uint64_t s = (uint64_t)wave_id_global(); s < a.slots; s += nw) {
+        if (a.c.kv[2 * s] == EMPTY_KEY) continue;
+        const uint64_t info = a.c.info[s];
+        if (!(info & VALID)) continue;
+        const uint32_t* base = a.pool.words + s * a.n * a.pool.W;
+        for (int cp = 0; cp < a.n; ++cp) {
+            if ((int)((info >> (3 * cp)) & 7u) != cp) continue;
+            const uint32_t* bm = base + (uint64_t)cp * a.pool.W;
+            int64_t cnt = 0;
+            for (uint32_t i = lane; i < a.pool.W; i += 64) cnt += __popc(bm[i]);
+            cnt = wave_sum(cnt);
+            if (lane == 0) ocnt[s * a.n + cp] += cnt;
+        }
+    }
+}
+
+// MNI support of every pattern slot (Section 2.2): the smallest orbit
+// domain; one thread per slot.
+__global__ void k_mni(MniArgs a, const int64_t* ocnt) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < a.slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t key = a.c.kv[2 * s];
         if (key == EMPTY_KEY) continue;
         const uint64_t info = a.c.info[s];
         int64_t best = -1;
-        if (info & VALID) {
-            const uint32_t* base = a.pool.words + s * a.n * a.pool.W;
+        if (info & VALID)
             for (int cp = 0; cp < a.n; ++cp) {
                 if ((int)((info >> (3 * cp)) & 7u) != cp) continue;
-                const uint32_t* bm = base + (uint64_t)cp * a.pool.W;
-                int64_t cnt = 0;
-                for (uint32_t i = lane; i < a.pool.W; i += 64) cnt += __popc(bm[i]);
-                cnt = wave_sum(cnt);
-                if (best < 0 || cnt < best) best = cnt;
+                const int64_t c = ocnt[s * a.n + cp];
+                if (best < 0 || c < best) best = c;
             }
+        if (best < 0) best = 0;
+        a.c.sup[s] = best;
+        const unsigned idx = atomicAdd(a.out_n, 1u);
+        if (idx < a.out_cap) {
+            a.out_key[idx] = key;
+            a.out_sup[idx] = best;
         }
-        if (lane == 0) {
-            if (best < 0) best = 0;
-            a.c.sup[s] = best;
-            unsigned idx = atomicAdd(a.out_n, 1u);
-            if (idx < a.out_cap) {
-                a.out_key[idx] = key;
-                a.out_sup[idx] = best;
-            }
-        }
+    }
+}
+
+// Move every QP of `from` into the smaller table `to` (same keys, values,
+// ordered subgraphs and pattern slots).
+__global__ void k_qp_rehash(QPTab from, uint64_t slots, QPTab to, uint32_t* flags) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = from.kv[2 * s];
+        if (key == EMPTY_KEY) continue;
+        const int64_t h = ht_probe(to.kv, to.mask, key, true, to.count, flags, OVF_QP);
+        if (h < 0) continue;
+        to.kv[2 * h + 1] = from.kv[2 * s + 1];
+        to.adj[h] = from.adj[s];
+        to.lab[h] = from.lab[s];
+        to.pat[h] = from.pat[s];
     }
 }
 
@@ -1763,6 +1802,15 @@ struct Tables {
         qcount.alloc(1);
         ccount.alloc(1);
     }
+    // Replace the QP part by an empty table of qc slots (the code part stays).
+    void take_qp(Tables& o) {
+        qkv.swap(o.qkv);
+        qadj.swap(o.qadj);
+        qlab.swap(o.qlab);
+        qpat.swap(o.qpat);
+        qcount.swap(o.qcount);
+        std::swap(qcap, o.qcap);
+    }
     void reset_qp() {
         k_init_table<<<grid_for((int64_t)qcap, TPB), TPB, 0, stream()>>>(qkv.p, qcap);
         FSM_LAUNCH_CHECK();
@@ -1828,6 +1876,9 @@ struct Miner {
     DBuf<uint8_t> f3;
     DBuf<uint32_t> pool, ppool;     // QP-position bitmaps, pattern-orbit bitmaps
     uint64_t pool_words = 0, ppool_words = 0;
+    uint64_t pool_budget = 0;     // bytes for the QP and pattern bitmap pools
+    uint32_t pass_W = 0;          // current domain pass: words per bitmap,
+    int32_t pass_rbase = 0;       // first rank of its slice
     DBuf<int32_t> lrank;
     DBuf<uint32_t> vinfo;
     DBuf<Rec> drec;     // device copy of the recording context of the join
@@ -1864,18 +1915,42 @@ struct Miner {
         R.q = {L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
                L.tab.qcount.p};
         R.c = {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
-        R.pool = {pool.p, lrank.p, W};
+        R.pool = {pool.p, lrank.p, pass_W, pass_rbase};
         R.flags = flags.p;
         R.n = L.n;
         return R;
     }
 
-    // Run a domain pass (retried with a larger QP table on overflow), then
-    // the canonical pass, the (pattern, orbit) merge and the MNI reduction;
-    // fills L.freq and the FREQ bits of the QP table.
+    // Bitmap words per (slot, position) in one pass: W (every rank at once)
+    // unless the QP and pattern pools of `slots` slots would exceed the
+    // pool budget; then the ranks are covered in slices.
+    uint32_t slice_words(uint64_t slots, int n) const {
+        const uint64_t per_word = slots * (uint64_t)n * sizeof(uint32_t);
+        const uint64_t fit = pool_budget / (per_word ? per_word : 1);
+        return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(W, fit));
+    }
+
+    void ensure_pool(DBuf<uint32_t>& p, uint64_t& have, uint64_t words) {
+        if (words > have) {
+            p.alloc(words);
+            have = words;
+        }
+        FSM_HIP(hipMemsetAsync(p.p, 0, words * sizeof(uint32_t), st));
+    }
+
+    // Domain passes of one level.  Pass 0 inserts the quick patterns
+    // (rerun with a larger table on overflow) and sets the domain bits of
+    // the first rank slice; the canonical pass follows; later passes
+    // repeat the enumeration for the remaining rank slices (lookups only).
+    // After every pass the slice's QP bitmaps are merged into (pattern,
+    // orbit) bitmaps and popcounted into per-orbit domain sizes; the MNI
+    // support is their minimum.  Fills L.freq and the FREQ bits of the QP
+    // table.  launch(R, pass) runs the level's domain kernel.
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
         uint64_t qcap = L.tab.qcap ? L.tab.qcap : std::max(qcap0(), qhint[L.n]);
+        const int64_t ranks = (int64_t)W * 32;
+        uint32_t w0 = W;
         for (int attempt = 0;; ++attempt) {
             L.st.domain_passes = attempt + 1;
             L.st.qp_capacity = (int64_t)qcap;
@@ -1884,15 +1959,14 @@ struct Miner {
                 fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
             if (L.tab.qcap != qcap) L.tab.alloc(qcap, 1);
             L.tab.reset_qp();
-            const uint64_t words = qcap * (uint64_t)L.n * W;
-            if (words > pool_words) {
-                pool.alloc(words);
-                pool_words = words;
-            }
-            FSM_HIP(hipMemsetAsync(pool.p, 0, words * sizeof(uint32_t), st));
+            // the pattern table gets up to 2 qcap slots
+            w0 = slice_words(3 * qcap, L.n);
+            pass_W = w0;
+            pass_rbase = 0;
+            ensure_pool(pool, pool_words, qcap * (uint64_t)L.n * w0);
             counters.zero();
             flags.zero();
-            launch(rec(L));
+            launch(rec(L), 0);
             const uint32_t f = scalar_to_host(flags.p);
             if (f & (ERR_MISSING | ERR_FILL))
                 fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", L.n, f);
@@ -1930,24 +2004,67 @@ struct Miner {
         }
         const unsigned npat = scalar_to_host(L.tab.ccount.p);
         L.st.patterns = npat;
-        const uint64_t pwords = ccap * (uint64_t)L.n * W;
-        if (pwords > ppool_words) {
-            ppool.alloc(pwords);
-            ppool_words = pwords;
-        }
-        FSM_HIP(hipMemsetAsync(ppool.p, 0, pwords * sizeof(uint32_t), st));
         QPTab q{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
                 L.tab.qcount.p};
-        MergeArgs ma{q, pool.p, ppool.p, W, L.n, L.tab.qcap * (uint64_t)L.n};
-        k_qp_merge<<<grid_for((int64_t)ma.items, TPB / 64, 1u << 16), TPB, 0, st>>>(ma);
-        FSM_LAUNCH_CHECK();
+        DBuf<int64_t> ocnt((size_t)(ccap * (uint64_t)L.n));
+        ocnt.zero();
         DBuf<uint64_t> okey(npat ? npat : 1);
         DBuf<int64_t> osup(npat ? npat : 1);
         DBuf<unsigned> on(1);
         on.zero();
-        MniArgs m{{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p},
-                  {ppool.p, lrank.p, W}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
-        k_mni<<<grid_for((int64_t)L.tab.ccap, TPB / 64, 1u << 16), TPB, 0, st>>>(m);
+        const CodeTab ct{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
+        // merge and count the slice of the pass just run
+        auto reduce_slice = [&](uint32_t wr) {
+            ensure_pool(ppool, ppool_words, ccap * (uint64_t)L.n * wr);
+            MergeArgs ma{q, pool.p, ppool.p, wr, L.n, L.tab.qcap * (uint64_t)L.n};
+            k_qp_merge<<<grid_for((int64_t)ma.items, TPB / 64, 1u << 16), TPB, 0, st>>>(ma);
+            FSM_LAUNCH_CHECK();
+            MniArgs m{ct, {ppool.p, lrank.p, wr, 0}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
+            k_orbit_count<<<grid_for((int64_t)L.tab.ccap, TPB / 64, 1u << 16), TPB, 0, st>>>(
+                m, ocnt.p);
+            FSM_LAUNCH_CHECK();
+        };
+        reduce_slice(w0);
+        // more slices to come: move the QPs into a table sized for them
+        // (an overflow rerun grows the table 16-fold), so that every later
+        // slice can be wider
+        if ((int64_t)w0 * 32 < ranks) {
+            const uint64_t want = pow2_at_least(2ull * nqp + 16);
+            if (want < qcap) {
+                Tables nt;
+                nt.alloc(want, 1);
+                nt.reset_qp();
+                flags.zero();
+                const QPTab to{nt.qkv.p, want - 1, nt.qadj.p, nt.qlab.p, nt.qpat.p, nt.qcount.p};
+                k_qp_rehash<<<grid_for((int64_t)qcap, TPB), TPB, 0, st>>>(q, qcap, to, flags.p);
+                FSM_LAUNCH_CHECK();
+                if (scalar_to_host(flags.p) & OVF_QP)
+                    fail(FSM_EDEVICE, "QP table compaction overflowed at size %d", L.n);
+                L.tab.take_qp(nt);
+                qcap = want;
+                q = QPTab{L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
+                          L.tab.qcount.p};
+            }
+        }
+        int slices = 1;
+        for (int64_t lo = (int64_t)w0 * 32; lo < ranks; ++slices) {
+            const uint32_t wr = slice_words(qcap + ccap, L.n);
+            pass_W = wr;
+            pass_rbase = (int32_t)lo;
+            ensure_pool(pool, pool_words, qcap * (uint64_t)L.n * wr);
+            counters.zero();
+            flags.zero();
+            launch(rec(L), slices);
+            const uint32_t f = scalar_to_host(flags.p);
+            if (f) fail(FSM_EDEVICE, "domain slice %d of size %d failed (flags %u)", slices, L.n, f);
+            reduce_slice(wr);
+            lo += (int64_t)wr * 32;
+        }
+        L.st.rank_slices = slices;
+        pass_W = W;
+        pass_rbase = 0;
+        MniArgs m{ct, {ppool.p, lrank.p, W, 0}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
+        k_mni<<<grid_for((int64_t)L.tab.ccap, TPB), TPB, 0, st>>>(m, ocnt.p);
         FSM_LAUNCH_CHECK();
         k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(
             q, L.tab.qcap, L.tab.ckv.p, L.tab.csup.p, dtg.p, L.n);
@@ -2004,7 +2121,7 @@ struct Miner {
 void Miner::level2() {
     Level& L = lv[2];
     L.n = 2;
-    auto launch = [&](Rec R) {
+    auto launch = [&](Rec R, int) {
         L2Args a{g->row, g->col, vf.p, g->vg, g->n, R, counters.p, nullptr, nullptr, nullptr, 0};
         k_level2<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
         FSM_LAUNCH_CHECK();
@@ -2057,7 +2174,7 @@ void Miner::build_gf() {
 void Miner::level3() {
     Level& L = lv[3];
     L.n = 3;
-    auto launch = [&](Rec R) {
+    auto launch = [&](Rec R, int) {
         L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), R, counters.p,
                  nullptr, nullptr, nullptr, 0};
         k_level3<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
@@ -2407,7 +2524,8 @@ void Miner::join(int n) {
         t.goff = G.goff.p; t.gcnt = G.gcnt.p; t.toff = G.toff.p;
         t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p;
         t.tile_p = G.tile_p;
-        t.bits = R.pool.words; t.W = R.pool.W; t.rec = drec.p; t.flags = R.flags;
+        t.bits = R.pool.words; t.W = R.pool.W; t.rbase = R.pool.rbase; t.rec = drec.p;
+        t.flags = R.flags;
         t.item_children = nullptr;
         t.pkey = pkey.p;
         t.pcode = pcode.p;
@@ -2424,16 +2542,19 @@ void Miner::join(int n) {
     FSM_HIP(hipEventCreate(&j0));
     FSM_HIP(hipEventCreate(&j1));
     try {
-        domain_level(L, [&](Rec R) {
-            if (ich.p) {
+        float join_total = 0.f;
+        domain_level(L, [&](Rec R, int pass) {
+            // recording: pass 0 sees every child and inserts every QP
+            if (ich.p && pass == 0) {
                 ich.zero();
                 iqp.zero();
                 R.item_qps = iqp.p;
             }
+            if (pass == 0) join_total = 0.f;   // a new attempt
             FSM_HIP(hipEventRecord(j0, st));
             if (G.ntiles > 0) {
                 TileArgs t = tile_args(R);
-                t.item_children = ich.p;
+                t.item_children = pass == 0 ? ich.p : nullptr;
                 switch (n) {
                     case 4: k_join_tiles<4><<<grid_persistent, TPB, 0, st>>>(t); break;
                     case 5: k_join_tiles<5><<<grid_persistent, TPB, 0, st>>>(t); break;
@@ -2444,11 +2565,12 @@ void Miner::join(int n) {
                 FSM_LAUNCH_CHECK();
             }
             FSM_HIP(hipEventRecord(j1, st));
+            float ms = 0;
+            FSM_HIP(hipEventSynchronize(j1));
+            FSM_HIP(hipEventElapsedTime(&ms, j0, j1));
+            join_total += ms;
         });
-        float ms = 0;
-        FSM_HIP(hipEventSynchronize(j1));
-        FSM_HIP(hipEventElapsedTime(&ms, j0, j1));
-        L.st.join_ms = ms;
+        L.st.join_ms = join_total;
     } catch (...) {
         (void)hipEventDestroy(j0);
         (void)hipEventDestroy(j1);
@@ -2557,6 +2679,14 @@ void Miner::run() {
     for (size_t x = 0; x < fmap.size(); ++x)
         if (fmap[x] >= 0) maxcount = std::max(maxcount, g->count[x]);
     W = (uint32_t)((maxcount + 31) / 32);
+    pass_W = W;
+    // QP and pattern bitmap pools may take 40% of the free device memory
+    {
+        size_t fr = 0, tot = 0;
+        FSM_HIP(hipMemGetInfo(&fr, &tot));
+        pool_budget = std::max<uint64_t>((uint64_t)(0.4 * (double)fr), (uint64_t)1 << 26);
+        if (opt.pool_budget_mib > 0) pool_budget = (uint64_t)opt.pool_budget_mib << 20;
+    }
     lrank.alloc((size_t)g->n);
     {
         DBuf<unsigned> lcnt((size_t)G * F);
@@ -2692,6 +2822,7 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
     o.record = bo.learn && bo.model ? 1 : 0;
     o.disable_pruning = bo.disable_pruning;
     o.tiles_per_wave = bo.tiles_per_wave;
+    o.pool_budget_mib = bo.pool_budget_mib;
     o.sampling_rate = 1.0;
     o.hash_capacity_min = bo.hash_capacity_min;
     o.pattern_capacity_min = bo.pattern_capacity_min;

@@ -299,3 +299,27 @@ def test_torch_allocator_and_stream(er3300):
         fsm.set_stream(None)
         fsm.use_torch_allocator(False)
     assert_same(got, oracle.mine(w["n"], w["src"], w["dst"], w["vertex_labels"], 10, 4))
+
+
+# ---------------------------------------------------------- rank slices
+
+def test_rank_slices_agree_with_golden_er3300():
+    # a 1 MiB bitmap budget forces one 32-rank slice per domain pass, so
+    # every level runs as many passes as its bitmaps have words
+    gold = load_golden("er3300_t10_s6")
+    w = synth.workload(gold["workload"])
+    say("er3300 with 1 MiB domain budget")
+    got = gpu_mine(w["n"], w["src"], w["dst"], w["vertex_labels"], gold["support"],
+                   gold["max_size"], pool_budget_mib=1)
+    assert_same(got.patterns, [(n, tuple(l), a, s) for n, l, a, s in gold["patterns"]])
+    assert all(got.stats["levels"][n]["rank_slices"] > 1 for n in range(2, 7))
+
+
+def test_rank_slices_agree_with_golden_cl100k():
+    gold = load_golden("cl100k_t10000_s5")
+    w = synth.workload(gold["workload"])
+    say("cl100k with 64 MiB domain budget")
+    got = gpu_mine(w["n"], w["src"], w["dst"], w["vertex_labels"], gold["support"],
+                   gold["max_size"], pool_budget_mib=64)
+    assert_same(got.patterns, [(n, tuple(l), a, s) for n, l, a, s in gold["patterns"]])
+    assert got.stats["levels"][5]["rank_slices"] >= 2
