@@ -1429,8 +1429,10 @@ __global__ void k_qp_canon(CanonArgs a) {
 
 struct MergeArgs {
     QPTab q;
-    const uint32_t* qbits;     // QP slot s, position p: bitmap s*n+p
-    uint32_t* pbits;           // pattern slot P, orbit slot o: bitmap P*n+o
+    const uint32_t* qbits;     // QP slot s, position p: bitmap s*n+p of Wsrc words
+    uint32_t* pbits;           // pattern slot P, orbit slot o: bitmap P*n+o of W words
+    uint32_t Wsrc;
+    uint32_t woff;             // words woff .. woff+W-1 of every QP bitmap
     uint32_t W;
     int n;
     uint64_t items;            // QP slots * n
@@ -1446,7 +1448,7 @@ __global__ __launch_bounds__(TPB) void k_qp_merge(MergeArgs a) {
         const uint64_t v = a.q.kv[2 * s + 1];
         if (a.q.kv[2 * s] == EMPTY_KEY || !(v & VALID)) continue;
         const uint32_t o = (uint32_t)(v >> (3 * p)) & 7u;
-        const uint32_t* src = a.qbits + it * a.W;
+        const uint32_t* src = a.qbits + it * a.Wsrc + a.woff;
         uint32_t* dst = a.pbits + ((uint64_t)a.q.pat[s] * a.n + o) * a.W;
         for (uint32_t w = lane; w < a.W; w += 64) {
             const uint32_t x = src[w];
@@ -1921,12 +1923,13 @@ struct Miner {
         return R;
     }
 
-    // Bitmap words per (slot, position) in one pass: W (every rank at once)
-    // unless the QP and pattern pools of `slots` slots would exceed the
-    // pool budget; then the ranks are covered in slices.
+    // Bitmap words per (QP slot, position) in one pass: W (every rank at
+    // once) unless the QP pool of `slots` slots would exceed half the pool
+    // budget; then the ranks are covered in slices.  (The pattern pool takes
+    // the other half: slices are merged into it in parts.)
     uint32_t slice_words(uint64_t slots, int n) const {
         const uint64_t per_word = slots * (uint64_t)n * sizeof(uint32_t);
-        const uint64_t fit = pool_budget / (per_word ? per_word : 1);
+        const uint64_t fit = pool_budget / 2 / (per_word ? per_word : 1);
         return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(W, fit));
     }
 
@@ -1959,8 +1962,7 @@ struct Miner {
                 fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
             if (L.tab.qcap != qcap) L.tab.alloc(qcap, 1);
             L.tab.reset_qp();
-            // the pattern table gets up to 2 qcap slots
-            w0 = slice_words(3 * qcap, L.n);
+            w0 = slice_words(qcap, L.n);
             pass_W = w0;
             pass_rbase = 0;
             ensure_pool(pool, pool_words, qcap * (uint64_t)L.n * w0);
@@ -2013,16 +2015,24 @@ struct Miner {
         DBuf<unsigned> on(1);
         on.zero();
         const CodeTab ct{L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
-        // merge and count the slice of the pass just run
+        // merge and count the slice of the pass just run (wr words per QP
+        // bitmap), in parts whose pattern bitmaps fit the budget
         auto reduce_slice = [&](uint32_t wr) {
-            ensure_pool(ppool, ppool_words, ccap * (uint64_t)L.n * wr);
-            MergeArgs ma{q, pool.p, ppool.p, wr, L.n, L.tab.qcap * (uint64_t)L.n};
-            k_qp_merge<<<grid_for((int64_t)ma.items, TPB / 64, 1u << 16), TPB, 0, st>>>(ma);
-            FSM_LAUNCH_CHECK();
-            MniArgs m{ct, {ppool.p, lrank.p, wr, 0}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
-            k_orbit_count<<<grid_for((int64_t)L.tab.ccap, TPB / 64, 1u << 16), TPB, 0, st>>>(
-                m, ocnt.p);
-            FSM_LAUNCH_CHECK();
+            const uint64_t per_word = ccap * (uint64_t)L.n * sizeof(uint32_t);
+            const uint32_t part = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>(wr, pool_budget / 2 / (per_word ? per_word : 1)));
+            for (uint32_t off = 0; off < wr; off += part) {
+                const uint32_t len = std::min(part, wr - off);
+                ensure_pool(ppool, ppool_words, ccap * (uint64_t)L.n * len);
+                MergeArgs ma{q, pool.p, ppool.p, wr, off, len, L.n, L.tab.qcap * (uint64_t)L.n};
+                k_qp_merge<<<grid_for((int64_t)ma.items, TPB / 64, 1u << 16), TPB, 0, st>>>(ma);
+                FSM_LAUNCH_CHECK();
+                MniArgs m{ct, {ppool.p, lrank.p, len, 0}, L.n, L.tab.ccap, okey.p, osup.p, on.p,
+                          npat};
+                k_orbit_count<<<grid_for((int64_t)L.tab.ccap, TPB / 64, 1u << 16), TPB, 0, st>>>(
+                    m, ocnt.p);
+                FSM_LAUNCH_CHECK();
+            }
         };
         reduce_slice(w0);
         // more slices to come: move the QPs into a table sized for them
@@ -2048,7 +2058,7 @@ struct Miner {
         }
         int slices = 1;
         for (int64_t lo = (int64_t)w0 * 32; lo < ranks; ++slices) {
-            const uint32_t wr = slice_words(qcap + ccap, L.n);
+            const uint32_t wr = slice_words(qcap, L.n);
             pass_W = wr;
             pass_rbase = (int32_t)lo;
             ensure_pool(pool, pool_words, qcap * (uint64_t)L.n * wr);
