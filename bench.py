@@ -128,6 +128,45 @@ def batch_comparison(fsm, synth):
             "exact_match_plain": same}
 
 
+def cost_model_leg(fsm, synth, max_size=5):
+    """The 1M-vertex, 37-label workload mined with plain table sizing and
+    with a cost model trained on the rows a recording call produced; both
+    must return identical results."""
+    import torch
+    w = synth.workload("cl1m")
+    g = fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"])
+    t = w["support"]
+    print(f"[bench] cost-model leg: cl1m n={w['n']} m={w['m']} t={t} sizes 2..{max_size}",
+          file=sys.stderr, flush=True)
+    rec = fsm.mine(g, t, max_size, record=True)
+    model = fsm.Model(fsm.FEATURES, seed=1)
+    loss = model.train(rec.train_x, rec.train_t, 800, 3e-3)
+
+    def timed(**kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fsm.mine(g, t, max_size, **kw)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    plain, tp = timed()
+    learned, tl = timed(mode=fsm.FSM_LEARNED, model=model)
+    print(f"[bench] cl1m plain {tp:.2f} s, learned {tl:.2f} s", file=sys.stderr, flush=True)
+    lv = lambda r, k: {n: r.stats["levels"][n][k] for n in r.stats["levels"] if n >= 4}
+    out = {"workload": "cl1m", "max_size": max_size, "patterns": len(plain),
+           "training_rows": int(len(rec.train_x)), "training_loss": round(loss, 4),
+           "plain_s": round(tp, 3), "learned_s": round(tl, 3), "speedup": round(tp / tl, 3),
+           "domain_passes_plain": lv(plain, "domain_passes"),
+           "domain_passes_learned": lv(learned, "domain_passes"),
+           "rank_slices_plain": lv(plain, "rank_slices"),
+           "rank_slices_learned": lv(learned, "rank_slices"),
+           "qp_predicted": lv(learned, "qp_predicted"), "qp_actual": lv(plain, "quick_patterns"),
+           "exact_match_plain": plain.patterns == learned.patterns}
+    model.close()
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +176,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-graph plain vs batched+learned comparison")
+    ap.add_argument("--cost-model-leg", action="store_true",
+                    help="also mine the 1M-vertex, 37-label workload (sizes 2..5) with plain "
+                         "and with learned table sizing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one elementwise int32 kernel that reads and "
                          "writes this many MiB (calibrates profiler byte counters)")
@@ -205,6 +247,7 @@ def main():
                     "valu": valu}
 
     batch = None if args.no_batch else batch_comparison(fsm, synth)
+    learned = cost_model_leg(fsm, synth) if args.cost_model_leg else None
 
     cpu = None
     exact = None
@@ -242,6 +285,8 @@ def main():
         "cpu_baseline": cpu,
         "batch": batch,
     }
+    if learned is not None:
+        out["cost_model"] = learned
     print(json.dumps(out), flush=True)
 
 

@@ -107,3 +107,36 @@ def test_learned_sizing_keeps_results_exact():
         st = got.stats["levels"][n]
         assert st["qp_predicted"] > 0
         assert st["qp_capacity"] >= st["quick_patterns"]
+
+
+def test_trained_model_saves_domain_passes():
+    # 24 graphs of the 256-graph workload mined one by one: without a model
+    # every level starts from the default table and reruns after overflows;
+    # with a model trained on the graphs mined before (online), the tables
+    # are sized from its predictions
+    ws = synth.batch_workload()[:24]
+    gs = [fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"]) for w in ws]
+
+    def passes(r):
+        return sum(r.stats["levels"][n]["domain_passes"] for n in (4, 5))
+
+    try:
+        plain = [fsm.mine(g, w["support"], 5) for g, w in zip(gs, ws)]
+        with fsm.Model(fsm.FEATURES, seed=3) as m:
+            learned = []
+            for g, w in zip(gs, ws):
+                r = fsm.mine(g, w["support"], 5, fsm.FSM_LEARNED, model=m, record=True)
+                learned.append(r)
+                m.train(r.train_x, r.train_t, 100, 3e-3)
+        for a, b in zip(plain, learned):
+            assert a.patterns == b.patterns
+        p0 = sum(passes(r) for r in plain)
+        p1 = sum(passes(r) for r in learned)
+        print(f"domain passes: plain {p0}, learned {p1} (minimum {2 * len(ws)})", flush=True)
+        assert p1 <= 0.75 * p0
+        # the first graph is sized before any training; from then on the
+        # predictions are calibrated and trained
+        assert all(r.stats["levels"][5]["qp_predicted"] > 0 for r in learned[1:])
+    finally:
+        for g in gs:
+            g.close()
