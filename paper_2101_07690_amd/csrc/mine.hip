@@ -2117,7 +2117,7 @@ struct Miner {
     void build_groups(const Level& P, int M, int64_t nwork, Groups& G);
     void sorted_pieces(DBuf<int64_t>& poff, DBuf<uint64_t>& key, DBuf<uint8_t>& code);
     void order_groups(const Level& P, int M, const ItemRows& IR, const float* y, Groups& G);
-    void proposal_thresholds(const ItemRows& IR, const float* y, int M, int64_t nitems,
+    void proposal_thresholds(const ItemRows& IR, const float* y, int64_t nitems,
                              DBuf<uint64_t>& thr);
 
     void run();
@@ -2337,26 +2337,24 @@ void Miner::order_groups(const Level& P, int M, const ItemRows& IR, const float*
     FSM_HIP(hipStreamSynchronize(st));
 }
 
-// Sampling proposal: keep rate min(1, lambda / sqrt(c_i / e_i)) for work
-// item i, where c_i is its predicted children and e_i its parent
-// embeddings (items whose parents each yield many children are redundant
-// and sampled thinner); lambda makes the expected work sum(rate_i c_i)
-// equal sampling_rate * sum(c_i), the uniform rate's.
-void Miner::proposal_thresholds(const ItemRows& IR, const float* y, int M, int64_t nitems,
+// Sampling proposal: keep rate min(1, lambda / c_i) for work item i, where
+// c_i is its predicted children -- every item's expected work is capped at
+// lambda, so items with few children (rare child patterns) are enumerated
+// whole and only heavy, redundant items are thinned; lambda makes the
+// expected work sum(rate_i c_i) equal sampling_rate * sum(c_i), the
+// uniform rate's.
+void Miner::proposal_thresholds(const ItemRows& IR, const float* y, int64_t nitems,
                                 DBuf<uint64_t>& thr) {
     std::vector<float> hy;
     std::vector<int32_t> hi;
-    std::vector<unsigned> hc;
     to_host(hy, y, (size_t)(IR.rows * MODEL_OUT));
     to_host(hi, IR.item.p, (size_t)IR.rows);
-    to_host(hc, IR.cnt.p, IR.cnt.n);
     const size_t R = (size_t)IR.rows;
     std::vector<double> c(R), wgt(R);
     double total = 0.0;
     for (size_t r = 0; r < R; ++r) {
         c[r] = std::expm1(std::max(0.0, (double)hy[2 * r]));
-        const double e = std::max(1u, hc[(size_t)hi[r] / (size_t)M]);
-        wgt[r] = 1.0 / std::sqrt(std::max(c[r] / e, 1e-3));
+        wgt[r] = 1.0 / std::max(c[r], 1.0);
         total += c[r];
     }
     const double budget = opt.sampling_rate * total;
@@ -2465,7 +2463,7 @@ void Miner::join(int n) {
     // sampled + learned: per-item keep rates from the model (the proposal)
     DBuf<uint64_t> ithr;
     if (learned && (opt.mode & FSM_SAMPLED) && IR.rows > 0 && opt.sampling_rate < 1.0)
-        proposal_thresholds(IR, y.p, M, nitems, ithr);
+        proposal_thresholds(IR, y.p, nitems, ithr);
     DBuf<unsigned long long> ich;
     DBuf<unsigned> iqp;
     if (record && IR.rows > 0) {

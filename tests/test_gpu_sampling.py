@@ -100,3 +100,21 @@ def test_proposal_thresholds_reach_materialised_levels():
     s = check_sample(exact, a, 0.1)
     assert a.stats["levels"][4]["stored"] > 0
     say(f"er3300 proposal: recall {s['recall']:.3f} by size {s['by_size']}")
+
+
+def test_learned_proposal_beats_uniform_at_low_rate(cl100k):
+    # at 5% of the work the proposal (every item's expected work capped, so
+    # items with few children are enumerated whole) recovers more of the
+    # exact patterns than uniform sampling
+    g, t, smax, exact, rec = cl100k
+    with fsm.Model(fsm.FEATURES, seed=4) as m:
+        m.train(rec.train_x, rec.train_t, 800, 3e-3)
+        a = fsm.mine(g, t, smax, fsm.FSM_SAMPLED | fsm.FSM_LEARNED, sampling_rate=0.05, seed=11,
+                     model=m)
+    u = fsm.mine(g, t, smax, fsm.FSM_SAMPLED, sampling_rate=0.05, seed=11)
+    sa, su = check_sample(exact, a, 0.3), check_sample(exact, u, 0.3)
+    wa, wu = emitted(a, (4, 5)), emitted(u, (4, 5))
+    say(f"rate 0.05: proposal recall {sa['recall']:.3f} work {wa} | uniform {su['recall']:.3f} "
+        f"work {wu}")
+    assert 0.8 * wu <= wa <= 1.25 * wu
+    assert sa["recall"] > su["recall"]
