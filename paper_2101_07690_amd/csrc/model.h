@@ -19,6 +19,9 @@ struct Model {
     DBuf<float> p, m, v, g;        // float32 master copy, moments, gradient
     DBuf<uint16_t> w;              // bfloat16 working copy
     DBuf<float> scal;              // loss accumulator
+    DBuf<float> bc;                // bias corrections of the current Adam step
+    DBuf<int> dstep;               // Adam steps taken (device copy)
+    static constexpr int GRAPH_STEPS = 8;   // train() replays a captured step from here on
     // per join size: actual / predicted quick patterns of the last level
     // sized with the current parameters (a summed expm1 of log-space
     // predictions is biased); 0 = none yet, reset by training

@@ -117,10 +117,23 @@ struct AdamArgs {
     const float* g;
     uint16_t* w;
     int64_t n;
-    float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^step
+    float lr, beta1, beta2, eps;
+    const float* bc;   // device: 1 - beta1^step, 1 - beta2^step
 };
 
+// Advance the device step counter and its bias corrections (one thread),
+// so that a captured Adam step replays with identical arguments.
+__global__ void k_adam_step(int* step, float beta1, float beta2, float* bc) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int s = *step + 1;
+        *step = s;
+        bc[0] = (float)(1.0 - pow((double)beta1, (double)s));
+        bc[1] = (float)(1.0 - pow((double)beta2, (double)s));
+    }
+}
+
 __global__ void k_adam(AdamArgs a) {
+    const float bc1 = a.bc[0], bc2 = a.bc[1];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float g = a.g[i];
@@ -128,7 +141,7 @@ __global__ void k_adam(AdamArgs a) {
         const float v = a.beta2 * a.v[i] + (1.f - a.beta2) * g * g;
         a.m[i] = m;
         a.v[i] = v;
-        const float p = a.p[i] - a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+        const float p = a.p[i] - a.lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
         a.p[i] = p;
         a.w[i] = f_to_bf(p);
     }
@@ -197,6 +210,8 @@ Model::Model(int in_dim, const float* init, uint64_t seed) : D(in_dim) {
     g.alloc((size_t)n);
     w.alloc((size_t)n);
     scal.alloc(1);
+    bc.alloc(2);
+    dstep.alloc(1);
     to_device(p.p, h.data(), (size_t)n);
     reset_optimizer();
     hipStream_t st = stream();
@@ -209,6 +224,7 @@ void Model::reset_optimizer() {
     hipStream_t st = stream();
     k_zero_f32<<<grid_for(n, 256), 256, 0, st>>>(m.p, n);
     k_zero_f32<<<grid_for(n, 256), 256, 0, st>>>(v.p, n);
+    k_zero_f32<<<1, 64, 0, st>>>(reinterpret_cast<float*>(dstep.p), 1);   // int 0
     FSM_LAUNCH_CHECK();
     step = 0;
 }
@@ -233,31 +249,64 @@ float Model::gradient(const float* dx, const float* dt, int64_t rows) {
     return scalar_to_host(scal.p) / (2.0f * (float)(rows > 0 ? rows : 1));
 }
 
-// Full-batch Adam steps; returns the loss measured in the last step's
-// forward pass (before its update).
-float Model::train(const float* dx, const float* dt, int64_t rows, int steps, float lr) {
-    hipStream_t st = stream();
-    for (double& c : calib) c = 0.0;   // calibration belongs to the old parameters
-    const float beta1 = 0.9f, beta2 = 0.999f;
-    for (int k = 0; k < steps; ++k) {
-        const bool last = k == steps - 1;
-        k_zero_f32<<<grid_for(n, 256), 256, 0, st>>>(g.p, n);
-        if (last) k_zero_f32<<<1, 64, 0, st>>>(scal.p, 1);
-        FSM_LAUNCH_CHECK();
-        if (rows > 0) {
-            FwdArgs a{w.p, D, dx, dt, rows, 1.0f / (float)rows, nullptr, g.p,
-                      last ? scal.p : nullptr};
-            k_mlp<<<model_grid(rows), TPB_M, lds_bytes(D, true), st>>>(a);
-            FSM_LAUNCH_CHECK();
-        }
-        ++step;
-        AdamArgs ad{p.p, m.p, v.p, g.p, w.p, n, lr, beta1, beta2, 1e-8f,
-                    (float)(1.0 - std::pow((double)beta1, step)),
-                    (float)(1.0 - std::pow((double)beta2, step))};
-        k_adam<<<grid_for(n, 256), 256, 0, st>>>(ad);
-        FSM_LAUNCH_CHECK();
+namespace {
+// Resources of one captured training loop, released on every exit path.
+struct Capture {
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Capture() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev) (void)hipEventDestroy(ev);
+        if (cs) (void)hipStreamDestroy(cs);
     }
-    if (steps > 0 && rows > 0) return scalar_to_host(scal.p) / (2.0f * (float)rows);
+};
+}  // namespace
+
+// Full-batch Adam steps; returns the loss measured in the last step's
+// forward pass (before its update).  A run of GRAPH_STEPS or more steps is
+// launch-bound (five small launches per step): one step is captured into a
+// HIP graph on a stream of its own, ordered after the library stream, and
+// replayed; shorter runs launch the same sequence directly.
+float Model::train(const float* dx, const float* dt, int64_t rows, int steps, float lr) {
+    for (double& c : calib) c = 0.0;   // calibration belongs to the old parameters
+    hipStream_t st = stream();
+    if (steps <= 0) {
+        FSM_HIP(hipStreamSynchronize(st));
+        return 0.f;
+    }
+    const float beta1 = 0.9f, beta2 = 0.999f;
+    auto enqueue = [&](hipStream_t s) {
+        k_zero_f32<<<grid_for(n, 256), 256, 0, s>>>(g.p, n);
+        k_zero_f32<<<1, 64, 0, s>>>(scal.p, 1);
+        if (rows > 0) {
+            FwdArgs a{w.p, D, dx, dt, rows, 1.0f / (float)rows, nullptr, g.p, scal.p};
+            k_mlp<<<model_grid(rows), TPB_M, lds_bytes(D, true), s>>>(a);
+        }
+        k_adam_step<<<1, 64, 0, s>>>(dstep.p, beta1, beta2, bc.p);
+        AdamArgs ad{p.p, m.p, v.p, g.p, w.p, n, lr, beta1, beta2, 1e-8f, bc.p};
+        k_adam<<<grid_for(n, 256), 256, 0, s>>>(ad);
+        FSM_LAUNCH_CHECK();
+    };
+    if (steps < GRAPH_STEPS) {
+        for (int k = 0; k < steps; ++k) enqueue(st);
+    } else {
+        Capture c;
+        FSM_HIP(hipStreamCreateWithFlags(&c.cs, hipStreamNonBlocking));
+        FSM_HIP(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+        FSM_HIP(hipEventRecord(c.ev, st));
+        FSM_HIP(hipStreamWaitEvent(c.cs, c.ev, 0));
+        FSM_HIP(hipStreamBeginCapture(c.cs, hipStreamCaptureModeThreadLocal));
+        enqueue(c.cs);
+        FSM_HIP(hipStreamEndCapture(c.cs, &c.graph));
+        FSM_HIP(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+        for (int k = 0; k < steps; ++k) FSM_HIP(hipGraphLaunch(c.exec, c.cs));
+        FSM_HIP(hipStreamSynchronize(c.cs));
+    }
+    step += steps;
+    if (rows > 0) return scalar_to_host(scal.p) / (2.0f * (float)rows);
     FSM_HIP(hipStreamSynchronize(st));
     return 0.f;
 }

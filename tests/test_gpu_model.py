@@ -140,3 +140,24 @@ def test_trained_model_saves_domain_passes():
     finally:
         for g in gs:
             g.close()
+
+
+def test_graph_replayed_training_matches_eager_steps():
+    # runs of >= 8 Adam steps replay a captured step; runs of 1 launch it
+    # directly.  Three rounds of 10 steps, with eager work (a prediction)
+    # between them, must track 30 single steps and the oracle's Adam.
+    D, B, lr = 12, 300, 1e-2
+    theta, x, t = rand_case(D, B, 7)
+    with fsm.Model(D, theta) as a, fsm.Model(D, theta) as b:
+        for rnd in range(3):
+            a.train(x, t, 10, lr)
+            ya = a.predict(x)
+            for _ in range(10):
+                b.train(x, t, 1, lr)
+            pa, pb = a.params(), b.params()
+            # float32 gradients summed by atomics in either order: compare
+            # the bulk of the parameters and the predictions
+            assert np.mean(np.abs(pa - pb) > 0.05 * lr * 10 * (rnd + 1)) < 0.01, rnd
+            assert np.max(np.abs(ya - b.predict(x))) < 1e-2, rnd
+    want = mlp.adam(theta, x, t, D, H, O, 30, lr)
+    assert mlp.loss(pa, x, t, D, H, O) == pytest.approx(mlp.loss(want, x, t, D, H, O), rel=1e-3)
