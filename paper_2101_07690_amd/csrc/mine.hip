@@ -1078,14 +1078,19 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                                              uint32_t ec, uint64_t PA, uint64_t L, int32_t pslot,
                                              int lu, int lw, LaneCache& c) {
     constexpr int M = N - 2;
+    // rank of every vertex by id: the vertices are distinct, so one compare
+    // per pair decides both ranks
     int rk[N];
 #pragma unroll
-    for (int p = 0; p < N; ++p) {
-        int r = 0;
+    for (int p = 0; p < N; ++p) rk[p] = 0;
 #pragma unroll
-        for (int q = 0; q < N; ++q) r += (cv[q] < cv[p]) ? 1 : 0;
-        rk[p] = r;
-    }
+    for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int q = p + 1; q < N; ++q) {
+            const int c = cv[p] < cv[q] ? 1 : 0;
+            rk[q] += c;
+            rk[p] += 1 - c;
+        }
     int rki = 0;
 #pragma unroll
     for (int p = 0; p < M; ++p)
