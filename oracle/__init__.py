@@ -53,6 +53,11 @@ def _load():
     lib.oracle_pattern_support.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p,
                                            i32p, ctypes.c_int32, i32p, ctypes.c_uint32]
     lib.oracle_pattern_support.restype = ctypes.c_int64
+    lib.oracle_mine_ex.argtypes = lib.oracle_mine.argtypes[:7] + [ctypes.c_int32,
+                                                                 lib.oracle_mine.argtypes[7]]
+    lib.oracle_mine_ex.restype = ctypes.c_int
+    lib.oracle_pattern_support_ex.argtypes = lib.oracle_pattern_support.argtypes + [ctypes.c_int32]
+    lib.oracle_pattern_support_ex.restype = ctypes.c_int64
     lib.oracle_count_connected.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p,
                                            i32p, ctypes.c_int32]
     lib.oracle_count_connected.restype = ctypes.c_int64
@@ -65,15 +70,16 @@ def _arr(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
-def mine(n_vertices, src, dst, labels, support, max_size):
-    """Exact frequent patterns of sizes 2..max_size (see module doc)."""
+def mine(n_vertices, src, dst, labels, support, max_size, induced=False):
+    """Exact frequent patterns of sizes 2..max_size (see module doc);
+    ``induced`` selects vertex-induced embeddings."""
     lib = _load()
     s, sp = _arr(src)
     d, dp = _arr(dst)
     lab, lp = _arr(labels)
     h = ctypes.c_void_p()
-    rc = lib.oracle_mine(int(n_vertices), int(s.size), sp, dp, lp, int(support),
-                         int(max_size), ctypes.byref(h))
+    rc = lib.oracle_mine_ex(int(n_vertices), int(s.size), sp, dp, lp, int(support),
+                            int(max_size), 1 if induced else 0, ctypes.byref(h))
     if rc != 0:
         raise ValueError("oracle_mine rejected its input")
     try:
@@ -109,15 +115,16 @@ def canonical(labels, adj):
     return tuple(int(x) for x in out[:n]), int(oadj.value)
 
 
-def pattern_support(n_vertices, src, dst, labels, plabels, padj):
+def pattern_support(n_vertices, src, dst, labels, plabels, padj, induced=False):
     """Exact MNI support of one connected pattern."""
     lib = _load()
     s, sp = _arr(src)
     d, dp = _arr(dst)
     lab, lp = _arr(labels)
     pl, plp = _arr(plabels)
-    r = lib.oracle_pattern_support(int(n_vertices), int(s.size), sp, dp, lp,
-                                   len(plabels), plp, ctypes.c_uint32(padj))
+    r = lib.oracle_pattern_support_ex(int(n_vertices), int(s.size), sp, dp, lp,
+                                      len(plabels), plp, ctypes.c_uint32(padj),
+                                      1 if induced else 0)
     if r < 0:
         raise ValueError("bad pattern")
     return int(r)

@@ -10,7 +10,12 @@ sequence) over all vertex orders), and every vertex order that reaches that
 minimum is one such bijection, so the image sets collected from all of them are
 exactly the MNI domains.
 
-Pure Python over all 2^|E| edge subsets: keep |E| <= ~12.
+In vertex-induced mode the subgraphs are the connected vertex sets with all
+their graph edges, and a bijection is an embedding when it carries the
+pattern's edges exactly onto those edges (non-edges onto non-edges).
+
+Pure Python over all 2^|E| edge subsets (or all vertex subsets): keep
+|E| <= ~12 (n <= ~12).
 """
 from __future__ import annotations
 
@@ -64,19 +69,35 @@ def _best_orders(verts, edges, labels):
     return best, orders
 
 
-def mine(n_vertices, src, dst, labels, support, max_size, with_counts=False):
-    """Same output format as ``oracle.mine``; optionally also the number of
-    connected edge-induced subgraphs per size."""
-    edges = _normalize(src, dst)
-    labels = [int(x) for x in labels]
-    domains = {}
-    counts = {}
+def _subgraphs(n_vertices, edges, max_size, induced):
+    """Every connected subgraph with 2..max_size vertices, once: all edge
+    subsets (edge-induced), or all vertex subsets with their induced edges
+    (vertex-induced)."""
+    if induced:
+        for k in range(2, max_size + 1):
+            for verts in itertools.combinations(range(n_vertices), k):
+                vs = set(verts)
+                sub = [e for e in edges if e[0] in vs and e[1] in vs]
+                if _connected(verts, sub):
+                    yield list(verts), sub
+        return
     m = len(edges)
     for mask in range(1, 1 << m):
         sub = [edges[i] for i in range(m) if mask >> i & 1]
         verts = sorted({v for e in sub for v in e})
-        if len(verts) > max_size or not _connected(verts, sub):
-            continue
+        if len(verts) <= max_size and _connected(verts, sub):
+            yield verts, sub
+
+
+def mine(n_vertices, src, dst, labels, support, max_size, with_counts=False, induced=False):
+    """Same output format as ``oracle.mine``; optionally also the number of
+    connected subgraphs per size.  ``induced``: vertex-induced subgraphs
+    (every connected vertex set with all the graph edges among it)."""
+    edges = _normalize(src, dst)
+    labels = [int(x) for x in labels]
+    domains = {}
+    counts = {}
+    for verts, sub in _subgraphs(int(n_vertices), edges, max_size, induced):
         counts[len(verts)] = counts.get(len(verts), 0) + 1
         code, orders = _best_orders(verts, sub, labels)
         dom = domains.setdefault(code, [set() for _ in verts])

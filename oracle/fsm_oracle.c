@@ -33,6 +33,12 @@
  *     whether some embedding maps c to u.  Every vertex of one orbit has the
  *     same image set, so sigma is the minimum over orbits of those counts.
  *
+ * Vertex-induced mode (oracle_mine_ex with induced = 1): an embedding must
+ * also map every non-edge of P onto a non-edge of G, i.e. its image is an
+ * induced subgraph (the vertex-induced reading of Section 2.1).  Deleting a
+ * non-cut vertex of an induced embedding leaves an induced embedding of the
+ * induced sub-pattern, so the growth and the drop-vertex check stay exact.
+ *
  * Also: a count of connected edge-induced subgraphs with a given number of
  * vertices (every connected vertex set, enumerated once by Wernicke's ESU
  * scheme, times the number of connected spanning edge subsets of its induced
@@ -318,6 +324,7 @@ static int olist_contains(const olist *l, const opat *p) {
 typedef struct {
     const ograph *g;
     const opat *p;
+    int induced;        /* 1: pattern non-edges must map onto non-edges */
     int order[OMAX];    /* matching order, order[0] = start vertex */
     int anchor[OMAX];   /* an earlier-matched pattern neighbour of order[d] */
     int32_t map[OMAX];  /* map[pattern vertex] = graph vertex */
@@ -340,6 +347,7 @@ static int search_from(osearch *s, int d) {
         for (int e = 0; e < d && ok; e++) {
             int y = s->order[e];
             if (p->e[x][y] && y != s->anchor[d] && !adjacent(g, s->map[y], c)) ok = 0;
+            if (s->induced && !p->e[x][y] && adjacent(g, s->map[y], c)) ok = 0;
         }
         if (!ok) continue;
         s->map[x] = c;
@@ -394,7 +402,7 @@ static void bylabel_free(obylabel *b) { free(b->verts); free(b->start); }
 /* Exact MNI support of pattern p, or -1 once it is certainly below t.
  * When `t` <= 0 the exact support is always returned. */
 static int64_t support_of(const ograph *g, const obylabel *bl, const opat *p,
-                          int64_t t) {
+                          int64_t t, int induced) {
     int orbit[OMAX];
     orbits(p, orbit);
     int64_t best = INT64_MAX;
@@ -405,7 +413,7 @@ static int64_t support_of(const ograph *g, const obylabel *bl, const opat *p,
         int64_t b = bl->start[l], e = bl->start[l + 1];
         int64_t found = 0, remaining = e - b;
         osearch s;
-        s.g = g; s.p = p;
+        s.g = g; s.p = p; s.induced = induced;
         plan_order(&s, c);
         for (int64_t i = b; i < e; i++) {
             s.map[c] = bl->verts[i];
@@ -454,9 +462,9 @@ static int subpatterns_frequent(const opat *q, const olist *prev) {
     return 1;
 }
 
-int oracle_mine(int64_t n_vertices, int64_t n_edges, const int32_t *src,
-                const int32_t *dst, const int32_t *labels, int64_t support,
-                int32_t max_size, oracle_result **out) {
+int oracle_mine_ex(int64_t n_vertices, int64_t n_edges, const int32_t *src,
+                   const int32_t *dst, const int32_t *labels, int64_t support,
+                   int32_t max_size, int32_t induced, oracle_result **out) {
     if (!out) return -1;
     *out = NULL;
     if (support < 1 || max_size < 2 || max_size > OMAX) return -1;
@@ -508,7 +516,7 @@ int oracle_mine(int64_t n_vertices, int64_t n_edges, const int32_t *src,
         for (int64_t ci = 0; ci < cand.len; ci++) {
             oentry *e = &cand.v[ci];
             if (k + 1 >= 3 && !subpatterns_frequent(&e->p, &cur)) continue;
-            e->support = support_of(&g, &bl, &e->p, support);
+            e->support = support_of(&g, &bl, &e->p, support, induced);
             if (e->support >= support) {
                 olist_push(&next, e);
                 olist_push(&all, e);
@@ -540,6 +548,12 @@ int oracle_mine(int64_t n_vertices, int64_t n_edges, const int32_t *src,
     graph_free(&g);
     *out = r;
     return 0;
+}
+
+int oracle_mine(int64_t n_vertices, int64_t n_edges, const int32_t *src,
+                const int32_t *dst, const int32_t *labels, int64_t support,
+                int32_t max_size, oracle_result **out) {
+    return oracle_mine_ex(n_vertices, n_edges, src, dst, labels, support, max_size, 0, out);
 }
 
 int64_t oracle_result_count(const oracle_result *r) { return r ? r->count : -1; }
@@ -586,10 +600,10 @@ int oracle_canonical(int32_t n, const int32_t *labels, uint32_t adj,
 
 /* Exact MNI support of one pattern (labels + LSB-first pair bits); the
  * pattern must be connected.  Returns -1 on bad input. */
-int64_t oracle_pattern_support(int64_t n_vertices, int64_t n_edges,
-                               const int32_t *src, const int32_t *dst,
-                               const int32_t *labels, int32_t n,
-                               const int32_t *plabels, uint32_t padj) {
+int64_t oracle_pattern_support_ex(int64_t n_vertices, int64_t n_edges,
+                                  const int32_t *src, const int32_t *dst,
+                                  const int32_t *labels, int32_t n,
+                                  const int32_t *plabels, uint32_t padj, int32_t induced) {
     if (n < 1 || n > OMAX) return -1;
     opat p;
     p.n = n;
@@ -603,10 +617,17 @@ int64_t oracle_pattern_support(int64_t n_vertices, int64_t n_edges,
     if (graph_build(&g, n_vertices, n_edges, src, dst, labels)) { graph_free(&g); return -1; }
     obylabel bl;
     if (bylabel_build(&g, &bl)) { graph_free(&g); return -1; }
-    int64_t s = support_of(&g, &bl, &p, 0);
+    int64_t s = support_of(&g, &bl, &p, 0, induced);
     bylabel_free(&bl);
     graph_free(&g);
     return s;
+}
+
+int64_t oracle_pattern_support(int64_t n_vertices, int64_t n_edges,
+                               const int32_t *src, const int32_t *dst,
+                               const int32_t *labels, int32_t n,
+                               const int32_t *plabels, uint32_t padj) {
+    return oracle_pattern_support_ex(n_vertices, n_edges, src, dst, labels, n, plabels, padj, 0);
 }
 
 /* ------------------------------------------- connected subgraph counting */

@@ -199,3 +199,64 @@ def test_rejects_bad_input():
     with pytest.raises(ValueError):
         oracle.mine(2, np.array([0], np.int32), np.array([5], np.int32),
                     np.array([0, 0], np.int32), 1, 3)
+
+
+# ------------------------------------------------------- vertex-induced mode
+
+def test_induced_clique_only_cliques():
+    # every vertex set of K_5 induces a clique: one pattern per size, the
+    # clique, with every vertex in its domain
+    s, d = edges_of(list(itertools.combinations(range(5), 2)))
+    res = oracle.mine(5, s, d, np.zeros(5, np.int32), 1, 5, induced=True)
+    assert [(n, bin(adj).count("1"), sup) for n, _, adj, sup in res] == \
+        [(k, k * (k - 1) // 2, 5) for k in range(2, 6)]
+    # edge-induced mining of the same graph finds every connected graph
+    assert len(oracle.mine(5, s, d, np.zeros(5, np.int32), 1, 5)) == 1 + 2 + 6 + 21
+
+
+def test_induced_four_cycle():
+    # C_4 induces: the edge (support 4), the wedge (every vertex is a middle
+    # and an end: 4), and C_4 itself (4); no path on 4 vertices
+    s, d = edges_of([(0, 1), (1, 2), (2, 3), (3, 0)])
+    res = by_size(oracle.mine(4, s, d, np.zeros(4, np.int32), 1, 4, induced=True))
+    assert [len(res[k]) for k in (2, 3, 4)] == [1, 1, 1]
+    assert res[3][0][2] == 4 and bin(res[3][0][1]).count("1") == 2
+    assert res[4][0][2] == 4 and bin(res[4][0][1]).count("1") == 4
+    # edge-induced also has the 4-path (support 4)
+    assert len(by_size(oracle.mine(4, s, d, np.zeros(4, np.int32), 1, 4))[4]) == 2
+
+
+def test_induced_triangle_has_no_wedge():
+    s, d = edges_of([(0, 1), (1, 2), (0, 2)])
+    res = by_size(oracle.mine(3, s, d, np.zeros(3, np.int32), 1, 3, induced=True))
+    assert len(res[3]) == 1 and bin(res[3][0][1]).count("1") == 3
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_induced_equals_edge_induced_on_forests(seed):
+    # in a forest the connected vertex sets induce exactly the connected edge
+    # subsets, so both semantics give the same result
+    rng = np.random.default_rng(seed)
+    n = 14
+    pairs = [(int(rng.integers(0, v)), v) for v in range(1, n) if rng.random() < 0.85]
+    s, d = edges_of(pairs)
+    lab = rng.integers(0, 2, n).astype(np.int32)
+    for t in (1, 2):
+        assert oracle.mine(n, s, d, lab, t, 5, induced=True) == oracle.mine(n, s, d, lab, t, 5)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_induced_oracle_matches_brute_force(seed):
+    s, d, lab = synth.tiny_graph(9000 + seed, 8, 13, 1 + seed % 3)
+    n = len(lab)
+    for t in (1, 2):
+        for smax in (4, 5):
+            want = brute.mine(n, s, d, lab, t, smax, induced=True)
+            assert oracle.mine(n, s, d, lab, t, smax, induced=True) == want, (seed, t, smax)
+
+
+def test_induced_pattern_support_agrees_with_mine():
+    s, d, lab = synth.tiny_graph(9100, 9, 14, 2)
+    n = len(lab)
+    for size, labs, adj, sup in oracle.mine(n, s, d, lab, 1, 4, induced=True):
+        assert oracle.pattern_support(n, s, d, lab, list(labs), adj, induced=True) == sup
