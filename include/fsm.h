@@ -71,7 +71,10 @@ enum {
     FSM_PLAIN = 0,    /* level-by-level exact join (Sections 3-4) */
     FSM_BATCHED = 1,  /* many graphs in one pass (fsm_mine_batch) */
     FSM_LEARNED = 2,  /* size join tables from a cost model (options.model) */
-    FSM_SAMPLED = 4   /* subgraph sampling during joining (Section 5) */
+    FSM_SAMPLED = 4,  /* subgraph sampling during joining (Section 5) */
+    FSM_INDUCED = 8   /* vertex-induced subgraphs: embeddings must also map
+                         pattern non-edges onto non-edges (a join keeps every
+                         connecting edge, C = E_c, Section 4.2) */
 };
 
 /* Join tile schedules (fsm_options.schedule).  Results never depend on it. */
@@ -142,7 +145,8 @@ typedef struct {
 typedef struct {
     int64_t support;          /* MNI threshold t >= 1 */
     int32_t max_size;         /* 2..7 */
-    uint32_t mode;            /* FSM_PLAIN or FSM_SAMPLED */
+    uint32_t mode;            /* FSM_PLAIN, or any of FSM_SAMPLED,
+                                 FSM_LEARNED, FSM_INDUCED */
     int32_t disable_pruning;  /* 1: skip the Section 4.5 pruning (results
                                  are identical; counters differ) */
     int32_t schedule;         /* join tile schedule: FSM_SCHEDULE_QUEUE
@@ -202,7 +206,7 @@ int64_t fsm_graph_edges(const fsm_graph *g);
  * aggregation).
  *   support    MNI threshold t (>= 1); a pattern is kept iff sigma >= t
  *   max_size   2..7
- *   mode       FSM_PLAIN (FSM_SAMPLED needs fsm_mine_ex)
+ *   mode       FSM_PLAIN or FSM_INDUCED (FSM_SAMPLED needs fsm_mine_ex)
  *   out        receives the result handle
  * Errors: FSM_EINVAL (NULL graph/out, support < 1, max_size outside 2..7,
  * unknown mode bits, FSM_SAMPLED here); FSM_EUNSUPPORTED when more than
@@ -240,7 +244,8 @@ int fsm_mine_batch(const fsm_graph *const *graphs, int32_t count,
 /* Options of fsm_mine_batch_ex.  Zero-initialise, then set fields. */
 typedef struct {
     int32_t max_size;           /* 2..6 (2..7 when count == 1) */
-    uint32_t mode;              /* FSM_PLAIN or FSM_BATCHED (same meaning) */
+    uint32_t mode;              /* FSM_PLAIN or FSM_BATCHED (same meaning),
+                                   with FSM_LEARNED and/or FSM_INDUCED */
     int64_t chunk_vertices;     /* >0: at most this many vertices in one
                                    union pass (a larger single graph gets a
                                    pass of its own); 0: the tuned value

@@ -25,6 +25,7 @@ FSM_PLAIN = 0
 FSM_BATCHED = 1
 FSM_LEARNED = 2
 FSM_SAMPLED = 4
+FSM_INDUCED = 8
 FSM_SCHEDULE_QUEUE = 0
 FSM_SCHEDULE_STATIC = 1
 FEATURE_LABELS = 16

@@ -147,7 +147,7 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
         if (opt->support < 1) fail(FSM_EINVAL, "fsm_mine: support must be >= 1");
         if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
             fail(FSM_EINVAL, "fsm_mine: max_size must be in [2, %d]", FSM_MAX_SIZE);
-        if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED))
+        if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED | FSM_INDUCED))
             fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
         if ((opt->mode & FSM_LEARNED) && !opt->model)
             fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
@@ -202,7 +202,7 @@ int fsm_mine_batch_ex(const fsm_graph* const* graphs, int32_t count, const int64
         if (count > 2048) fail(FSM_EUNSUPPORTED, "fsm_mine_batch: at most 2048 graphs");
         if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
             fail(FSM_EINVAL, "fsm_mine_batch: max_size must be in [2, %d]", FSM_MAX_SIZE);
-        if (opt->mode & ~(uint32_t)(FSM_BATCHED | FSM_LEARNED))
+        if (opt->mode & ~(uint32_t)(FSM_BATCHED | FSM_LEARNED | FSM_INDUCED))
             fail(FSM_EINVAL, "fsm_mine_batch: unsupported mode bits 0x%x", opt->mode);
         if (opt->chunk_vertices < 0) fail(FSM_EINVAL, "fsm_mine_batch: chunk_vertices < 0");
         if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)

@@ -468,6 +468,7 @@ struct L3Args {
     const int64_t* offsets;
     int32_t* out;
     int64_t out_rows;
+    int induced = 0;       // vertex-induced: a wedge only when u !~ w
 };
 
 __device__ __forceinline__ void decode_pair(int64_t r, int32_t* a, int32_t* b) {
@@ -527,6 +528,7 @@ __global__ void k_piece_fill(const int32_t* row, const int32_t* col, const int32
 // One wave per centre c; lanes over neighbour pairs u < w.  Each pair is a
 // wedge (c; u, w) stored (c, u, w); when c < u and u ~ w it is also the
 // triangle stored (c, u, w) (each triangle once, at its smallest vertex).
+// Vertex-induced mode drops the wedges whose ends are adjacent.
 // QP = (type, labels in stored order).
 template <int MODE>
 __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
         for (int64_t r0 = 0; r0 < npairs; r0 += 64) {
             const int64_t r = r0 + lane;
             int32_t u = -1, w = -1;
-            bool tri = false;
+            bool tri = false, wedge = false;
             int lu = 0, lw = 0;
             if (r < npairs) {
                 int32_t ia, ib;
@@ -556,7 +558,9 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
                 w = a.col[rb + ib];
                 lu = a.vf[u];
                 lw = a.vf[w];
-                tri = c < u && has_edge(a.nh, u, w);
+                const bool uw = (a.induced || c < u) && has_edge(a.nh, u, w);
+                tri = c < u && uw;
+                wedge = !(a.induced && uw);
             }
             const uint64_t L = (uint64_t)lc | (uint64_t)lu << 6 | (uint64_t)lw << 12 | gid << 48;
             const uint64_t kw = gid << 19 | (uint64_t)lc << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
@@ -565,8 +569,10 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
             const int32_t v[3] = {(int32_t)c, u, w};
             if (MODE == MODE_DOMAIN) {
                 if (u >= 0) {
-                    record<3>(a.R, kw, L, Aw, v);
-                    ++emit;
+                    if (wedge) {
+                        record<3>(a.R, kw, L, Aw, v);
+                        ++emit;
+                    }
                     if (tri) {
                         record<3>(a.R, kt, L, add_edge(Aw, 1, 2), v);
                         ++emit;
@@ -575,7 +581,7 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
             } else {
                 int64_t sw = -1, stt = -1;
                 if (u >= 0) {
-                    sw = frequent_slot(a.R, kw);
+                    if (wedge) sw = frequent_slot(a.R, kw);
                     if (tri) stt = frequent_slot(a.R, kt);
                 }
                 int64_t cnum = (sw >= 0 ? 1 : 0) + (stt >= 0 ? 1 : 0);
@@ -631,6 +637,7 @@ struct JoinArgs {
     uint64_t seed;
     uint64_t sample_thr;     // keep a piece when its hash is below this
     const uint64_t* item_thr;   // or, when set, below the threshold of its work item
+    int induced;             // vertex-induced: the pieces' own edges are induced, C = E_c
     int64_t* counts;
     const int64_t* offsets;
     int32_t* out;
@@ -717,7 +724,7 @@ __device__ int children(const JoinArgs& a, const uint8_t* f3, const int32_t (&cv
                     }
                 }
             }
-            if (!sub) break;
+            if (!sub || a.induced) break;
             sub = (sub - 1) & ec;
         }
     }
@@ -809,13 +816,18 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                     if (ok) {
                         const int lu = a.vf[u], lw = a.vf[w];
                         if (centre) {
-                            if (f3_at(f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
-                            if (f3_at(f3, a.F, 1, lk, lu, lw)) {
+                            const bool fw = f3_at(f3, a.F, 0, lk, lu, lw);
+                            const bool ft = f3_at(f3, a.F, 1, lk, lu, lw);
+                            bool uw = false;
+                            if (ft || (a.induced && fw)) {
                                 bytes += 8;
-                                if (has_edge(a.nh, u, w)) types |= 1u << PIECE_TR;
+                                uw = has_edge(a.nh, u, w);
                             }
-                        } else {
-                            if (f3_at(f3, a.F, 0, lu, lk, lw)) types |= 1u << PIECE_KL;
+                            if (fw && !(a.induced && uw)) types |= 1u << PIECE_KC;
+                            if (ft && uw) types |= 1u << PIECE_TR;
+                        } else if (f3_at(f3, a.F, 0, lu, lk, lw)) {
+                            // vertex-induced: k !~ w (else it is the triangle)
+                            if (!a.induced || !has_edge(a.nh, k, w)) types |= 1u << PIECE_KL;
                         }
                     }
                 }
@@ -1009,6 +1021,7 @@ struct TileArgs {
     uint64_t seed;
     uint64_t sample_thr;
     const uint64_t* item_thr;   // per work item sampling thresholds, or null
+    int induced;                // vertex-induced: induced pieces, C = E_c only
 };
 
 constexpr uint32_t RANK_MASK = (1u << 26) - 1;
@@ -1134,6 +1147,8 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
         const uint32_t r0 =
             rpar | eku | (t == PIECE_KC ? ekw : (t == PIECE_KL ? euw : (ekw | euw)));
         const uint32_t allowed = t == PIECE_KL ? allow_kl : allow_both;
+        // vertex-induced: the one child keeps every connecting edge
+        if (a.induced && allowed != ec) continue;
         const uint64_t kbase = (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)t << 30 |
                                (uint64_t)lu << 24 | (uint64_t)lw << 18;
         uint32_t sub = allowed;
@@ -1186,7 +1201,7 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                 }
                 ++got;
             }
-            if (!sub) break;
+            if (!sub || a.induced) break;
             sub = (sub - 1) & allowed;
         }
     }
@@ -1272,13 +1287,18 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 lru = (int32_t)(iu & RANK_MASK);
                 lrw = (int32_t)(iw & RANK_MASK);
                 if (centre) {
-                    if (f3_at(f3, a.F, 0, lk, lu, lw)) types |= 1u << PIECE_KC;
-                    if (f3_at(f3, a.F, 1, lk, lu, lw)) {
+                    const bool fw = f3_at(f3, a.F, 0, lk, lu, lw);
+                    const bool ft = f3_at(f3, a.F, 1, lk, lu, lw);
+                    bool uw = false;
+                    if (ft || (a.induced && fw)) {
                         bytes += 8;
-                        if (has_edge(a.nh, u, w)) types |= 1u << PIECE_TR;
+                        uw = has_edge(a.nh, u, w);
                     }
+                    if (fw && !(a.induced && uw)) types |= 1u << PIECE_KC;
+                    if (ft && uw) types |= 1u << PIECE_TR;
                 } else if (f3_at(f3, a.F, 0, lu, lk, lw)) {
-                    types |= 1u << PIECE_KL;
+                    // vertex-induced: k !~ w (else it is the triangle)
+                    if (!a.induced || !has_edge(a.nh, k, w)) types |= 1u << PIECE_KL;
                 }
             }
         }
@@ -2192,6 +2212,7 @@ void Miner::level3() {
     auto launch = [&](Rec R, int) {
         L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), R, counters.p,
                  nullptr, nullptr, nullptr, 0};
+        a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
         k_level3<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
         FSM_LAUNCH_CHECK();
     };
@@ -2492,6 +2513,7 @@ void Miner::join(int n) {
         a.prune = opt.disable_pruning ? 0 : 1;
         a.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
         a.seed = opt.seed; a.sample_thr = thr; a.item_thr = ithr.p;
+        a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
         a.counts = counts; a.offsets = offsets; a.out = out; a.out_rows = rows;
         return a;
     };
@@ -2548,6 +2570,7 @@ void Miner::join(int n) {
         t.prune = opt.disable_pruning ? 0 : 1;
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
         t.seed = opt.seed; t.sample_thr = thr; t.item_thr = ithr.p;
+        t.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
         t.dtab = dtab.p;
         return t;
     };
@@ -2750,6 +2773,7 @@ void Miner::run() {
                                      int32_t* out, int64_t rows) {
                 L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), rec(L), counters.p,
                          counts, offsets, out, rows};
+                a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
                 if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
                 else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
                 FSM_LAUNCH_CHECK();
@@ -2830,7 +2854,7 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
     fsm_options o;
     memset(&o, 0, sizeof(o));
     o.max_size = bo.max_size;
-    o.mode = bo.mode & FSM_LEARNED;
+    o.mode = bo.mode & (FSM_LEARNED | FSM_INDUCED);
     o.model = bo.model;
     o.record = bo.learn && bo.model ? 1 : 0;
     o.disable_pruning = bo.disable_pruning;
