@@ -1,0 +1,160 @@
+"""Pins of the sampled-join oracle (oracle.sampled) on the CPU: with no
+sampling it reproduces the exact miner and produces every connected subgraph
+exactly once; its hash is the published splitmix64; a sampled group keeps
+exactly min(size, cap) members, each with probability cap/size; and the
+sampled runs follow Section 5 (all iterations of a short loop, lower-bound
+supports, more patterns with larger thresholds)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.brute as brute
+import oracle.sampled as sp
+
+
+def graph(seed, n, m, num_labels):
+    rng = np.random.default_rng(seed)
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    pick = rng.choice(len(pairs), size=m, replace=False)
+    src = np.array([pairs[p][0] for p in pick], np.int32)
+    dst = np.array([pairs[p][1] for p in pick], np.int32)
+    return src, dst, rng.integers(0, num_labels, n).astype(np.int32)
+
+
+def as_map(res):
+    return {(n, labs, adj): sup for n, labs, adj, sup in res}
+
+
+def test_splitmix64_published_outputs():
+    # splitmix64 seeded with 0: state advances by the golden gamma, output is
+    # the finalizer of the state (Steele, Lea and Flood 2014)
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    s = 0
+    for w in want:
+        s = (s + 0x9E3779B97F4A7C15) & sp.M64
+        assert sp.mix64(s) == w
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("induced", [False, True])
+def test_unsampled_equals_exact_miner(seed, induced):
+    src, dst, lab = graph(seed, 16, 30, 2 + seed % 3)
+    for t, smax in ((2, 5), (3, 5)):
+        want = oracle.mine(16, src, dst, lab, t, smax, induced=induced)
+        assert sp.mine(16, src, dst, lab, t, smax, induced=induced) == want
+        assert sp.mine(16, src, dst, lab, t, smax, induced=induced, prune=False) == want
+
+
+@pytest.mark.parametrize("induced", [False, True])
+def test_every_subgraph_produced_once(induced):
+    # t = 1, no pruning: the join meets every connected subgraph once
+    src, dst, lab = graph(9, 11, 16, 1)
+    _, counts = sp.mine(11, src, dst, lab, 1, 5, prune=False, with_counts=True, induced=induced)
+    _, want = brute.mine(11, src, dst, lab, 1, 5, with_counts=True, induced=induced)
+    assert all(counts[k] == want[k] for k in (3, 4, 5))
+
+
+def test_threshold_keeps_a_uniform_fixed_size_sample():
+    # Section 5: a loop longer than the threshold is sampled uniformly down
+    # to the threshold; a shorter one runs in full
+    members, cap, trials = 10, 3, 4000
+    hits = np.zeros(members)
+    for seed in range(trials):
+        h = [sp.unit_hash(seed, 7 << 48, 5, m) for m in range(members)]
+        thr = sp.threshold(h, cap)
+        kept = [x <= thr for x in h]
+        assert sum(kept) == cap
+        hits += kept
+    p = cap / members
+    sd = math.sqrt(p * (1 - p) / trials)
+    assert np.all(np.abs(hits / trials - p) < 5.5 * sd)
+    assert sp.threshold([3, 1, 2], 3) == sp.M64 and sp.threshold([3, 1, 2], 2) == 2
+    # all pairs of members are equally likely together (no ordering bias)
+    pairs = {}
+    for seed in range(trials):
+        h = [sp.unit_hash(seed, 9 << 48, 1, m) for m in range(4)]
+        thr = sp.threshold(h, 2)
+        key = tuple(m for m in range(4) if h[m] <= thr)
+        pairs[key] = pairs.get(key, 0) + 1
+    assert len(pairs) == 6 and min(pairs.values()) > trials / 6 * 0.85
+
+
+def test_star_size4_closed_form():
+    # K_{1,5} (centre 0), one label, t = 1: each 3-star {0, a, b, c}
+    # (a < b < c) splits into the wedge a-0-b and the edge 0-c at k = 0; with
+    # ST x it is produced iff 0's edge group keeps (0, c) (x of 5) and 0's
+    # key group keeps the wedge (x^2 of the 10 wedges at 0)
+    src = np.zeros(5, np.int32)
+    dst = np.arange(1, 6, dtype=np.int32)
+    lab = np.zeros(6, np.int32)
+    for x, seed in itertools.product((1, 2, 3), (0, 5, 17)):
+        res, counts = sp.mine(6, src, dst, lab, 1, 4, join_threshold=x, seed=seed,
+                              with_counts=True)
+        eh = {c: sp.edge_hash(seed, 0, c) for c in range(1, 6)}
+        ethr = sp.threshold(list(eh.values()), x)
+        wh = {(a, b): sp.piece_hash(seed, 4, 0, sp.KC, a, b)
+              for a, b in itertools.combinations(range(1, 6), 2)}
+        wthr = sp.threshold(list(wh.values()), x * x)
+        want = sum(1 for (a, b), h in wh.items() for c in range(b + 1, 6)
+                   if h <= wthr and eh[c] <= ethr)
+        assert counts[4] == want, (x, seed)
+        assert counts[3] == 10
+        assert want <= min(x, 5) * min(x * x, 10)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_matching_keeps_t_per_vertex(seed):
+    # t = 1 (every labelled edge frequent): the vertex credited with a wedge
+    # is its centre, with a triangle its smallest vertex; each keeps
+    # min(t_m, credited) of them
+    src, dst, lab = graph(40 + seed, 14, 26, 2)
+    adj = {v: set() for v in range(14)}
+    for a, b in zip(src, dst):
+        adj[int(a)].add(int(b))
+        adj[int(b)].add(int(a))
+    credited = {c: len(adj[c]) * (len(adj[c]) - 1) // 2 +
+                sum(1 for u, w in itertools.combinations(sorted(adj[c]), 2)
+                    if c < u and w in adj[u]) for c in range(14)}
+    for tm in (1, 2, 5):
+        _, counts = sp.mine(14, src, dst, lab, 1, 3, match_threshold=tm, seed=seed,
+                            with_counts=True)
+        assert counts[3] == sum(min(tm, c) for c in credited.values())
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("induced", [False, True])
+def test_sampled_runs_are_lower_bounds_and_nested(seed, induced):
+    src, dst, lab = graph(60 + seed, 16, 32, 2)
+    exact = as_map(oracle.mine(16, src, dst, lab, 2, 5, induced=induced))
+    prev = None
+    for x in (1, 2, 3, 4):
+        got = as_map(sp.mine(16, src, dst, lab, 2, 5, join_threshold=x, seed=seed,
+                             induced=induced))
+        assert all(k in exact and s <= exact[k] for k, s in got.items())
+        # sizes 2 and 3 are not sampled by the join
+        assert {k: s for k, s in got.items() if k[0] <= 3} == \
+               {k: s for k, s in exact.items() if k[0] <= 3}
+        if prev is not None:   # kept sets are nested in the threshold
+            assert all(k in got and s <= got[k] for k, s in prev.items())
+        prev = got
+    # a threshold above every group size keeps everything
+    assert as_map(sp.mine(16, src, dst, lab, 2, 5, join_threshold=64, seed=seed,
+                          induced=induced)) == exact
+    assert as_map(sp.mine(16, src, dst, lab, 2, 5, match_threshold=10 ** 6, seed=seed,
+                          induced=induced)) == exact
+    for tm in (1, 3):
+        got = as_map(sp.mine(16, src, dst, lab, 2, 5, match_threshold=tm, seed=seed,
+                             induced=induced))
+        assert all(k in exact and s <= exact[k] for k, s in got.items())
+
+
+def test_rate_one_is_exact_and_rate_sampling_is_a_lower_bound():
+    src, dst, lab = graph(77, 16, 32, 2)
+    exact = as_map(oracle.mine(16, src, dst, lab, 2, 5))
+    assert as_map(sp.mine(16, src, dst, lab, 2, 5, rate=1.0, seed=3)) == exact
+    got = as_map(sp.mine(16, src, dst, lab, 2, 5, rate=0.3, seed=3))
+    assert all(k in exact and s <= exact[k] for k, s in got.items())
+    assert got != exact
