@@ -169,6 +169,18 @@ typedef struct {
                                  a level, in MiB; 0: 40% of the free memory.
                                  Bitmaps larger than this are computed in
                                  vertex-rank slices, one join pass each */
+    int64_t join_threshold;   /* >0: sampling threshold x of the joins
+                                 (Section 5, "ST x"): every join keeps x^2 of
+                                 the stored size-3 subgraphs of each key
+                                 group (those containing the joining vertex)
+                                 and the size-4 join x of its edges; a group
+                                 with fewer keeps all.  0: off.  In
+                                 [0, 2^20]; not with FSM_SAMPLED */
+    int64_t match_threshold;  /* >0: matching sampling threshold t (Section
+                                 5): t of the size-3 subgraphs credited to
+                                 each vertex (a wedge to its centre, a
+                                 triangle to its smallest vertex) are kept
+                                 and joined.  0: off */
 } fsm_options;
 
 /* Allocation hooks used for all device memory of later calls (e.g. a
@@ -219,9 +231,14 @@ int fsm_mine(const fsm_graph *g, int64_t support, int32_t max_size,
 /* fsm_mine with options.  FSM_SAMPLED keeps each size-3 piece of a key group
  * at every join with probability sampling_rate, decided by a counter-based
  * hash of (seed, level, joining vertex, the piece's vertices) -- subgraph
- * sampling during joining (Section 5); supports are then MNI over the
- * sampled embeddings (a lower bound).  Errors as fsm_mine, plus FSM_EINVAL
- * for a sampling rate outside (0, 1]. */
+ * sampling during joining (Section 5).  join_threshold and match_threshold
+ * instead keep a fixed number of every group's members, a uniform sample
+ * without replacement: the members whose counter-based hash is at most the
+ * group's cap-th smallest.  Sampled supports are MNI over the sampled
+ * embeddings (a lower bound of the exact ones); results are reproducible
+ * for a seed.  Errors as fsm_mine, plus FSM_EINVAL for a sampling rate
+ * outside (0, 1], a threshold out of range, or join_threshold together
+ * with FSM_SAMPLED. */
 int fsm_mine_ex(const fsm_graph *g, const fsm_options *opt, fsm_result **out);
 
 /* Mine many graphs in one pass (batched mode): every level runs as one

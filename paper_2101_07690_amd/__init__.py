@@ -95,7 +95,8 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("record", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
-                ("pool_budget_mib", ctypes.c_int64)]
+                ("pool_budget_mib", ctypes.c_int64), ("join_threshold", ctypes.c_int64),
+                ("match_threshold", ctypes.c_int64)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -354,11 +355,17 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          sampling_rate: float = 1.0, seed: int = 0, disable_pruning: bool = False,
          hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
          record: bool = False, schedule: int = FSM_SCHEDULE_QUEUE,
-         tiles_per_wave: int = 0, pool_budget_mib: int = 0) -> Result:
+         tiles_per_wave: int = 0, pool_budget_mib: int = 0, join_threshold: int = 0,
+         match_threshold: int = 0) -> Result:
     """Frequent patterns of sizes 2..max_size with MNI support >= support.
     ``model`` (a Model with FEATURES inputs) sizes the join tables when
-    ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows."""
+    ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows.
+    ``join_threshold`` x samples x^2 size-3 subgraphs per key group at every
+    join (and x edges at the size-4 join), ``match_threshold`` t keeps t
+    size-3 subgraphs per vertex in matching (Section 5, seeded by ``seed``)."""
     o = Options()
+    o.join_threshold = int(join_threshold)
+    o.match_threshold = int(match_threshold)
     o.model = model.handle.value if model is not None else None
     o.record = 1 if record else 0
     o.schedule = int(schedule)

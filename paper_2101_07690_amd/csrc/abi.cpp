@@ -163,6 +163,11 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
         if ((opt->mode & FSM_SAMPLED) &&
             !(opt->sampling_rate > 0.0 && opt->sampling_rate <= 1.0))
             fail(FSM_EINVAL, "fsm_mine: sampling_rate must be in (0, 1]");
+        if (opt->join_threshold < 0 || opt->join_threshold > (int64_t)1 << 20)
+            fail(FSM_EINVAL, "fsm_mine: join_threshold must be in [0, 2^20]");
+        if (opt->match_threshold < 0) fail(FSM_EINVAL, "fsm_mine: match_threshold < 0");
+        if (opt->join_threshold > 0 && (opt->mode & FSM_SAMPLED))
+            fail(FSM_EINVAL, "fsm_mine: join_threshold and FSM_SAMPLED are exclusive");
         fsm_result* r = new fsm_result();
         try {
             mine(g, *opt, r);

@@ -249,6 +249,14 @@ __device__ __forceinline__ bool has_edge(const NbrHash& H, int32_t b, int32_t x)
     }
 }
 
+// Vertex-induced mode: graph edges between frequent-label vertices whose
+// labelled edge is infrequent (not in G_f), in tables of the same layout
+// (off null when there are none).  Such an edge inside a vertex set makes
+// its induced pattern infrequent, so the set is never a subgraph to keep.
+__device__ __forceinline__ bool blocked(const NbrHash& X, int32_t b, int32_t x) {
+    return X.off != nullptr && has_edge(X, b, x);
+}
+
 // wave index, kept in a scalar register so wave-uniform work stays scalar
 __device__ __forceinline__ int wave_id_global() {
     return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (TPB / 64) + (threadIdx.x >> 6)));
@@ -295,9 +303,10 @@ __global__ void k_vertex_flabel(const int32_t* lab, const int32_t* vg, int NL, i
 }
 
 // frequent-edge subgraph G_f: keep (v, w) when both labels are frequent and
-// the labelled edge is frequent
+// the labelled edge is frequent (want = 1), or infrequent (want = 0: the
+// edges a vertex-induced subgraph must not contain)
 __global__ void k_gf_count(const int32_t* row, const int32_t* col, const int32_t* vf,
-                           const int32_t* vg, int64_t n, const uint8_t* freq2, int F,
+                           const int32_t* vg, int64_t n, const uint8_t* freq2, int F, int want,
                            int64_t* cnt) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -307,14 +316,14 @@ __global__ void k_gf_count(const int32_t* row, const int32_t* col, const int32_t
         if (a >= 0)
             for (int32_t e = row[v]; e < row[v + 1]; ++e) {
                 int b = vf[col[e]];
-                if (b >= 0 && f2[a * F + b]) ++c;
+                if (b >= 0 && (f2[a * F + b] != 0) == (want != 0)) ++c;
             }
         cnt[v] = c;
     }
 }
 
 __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t* vf,
-                          const int32_t* vg, int64_t n, const uint8_t* freq2, int F,
+                          const int32_t* vg, int64_t n, const uint8_t* freq2, int F, int want,
                           const int64_t* off, int64_t total, int32_t* frow, int32_t* fcol) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -327,7 +336,7 @@ __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t*
         for (int32_t e = row[v]; e < row[v + 1]; ++e) {
             int32_t w = col[e];
             int b = vf[w];
-            if (b >= 0 && f2[a * F + b]) fcol[o++] = w;
+            if (b >= 0 && (f2[a * F + b] != 0) == (want != 0)) fcol[o++] = w;
         }
     }
 }
@@ -455,6 +464,103 @@ __global__ __launch_bounds__(TPB) void k_level2(L2Args a) {
 
 // --------------------------------------------------------------- level 3
 
+// ------------------------------------------------------------- sampling
+//
+// Subgraph sampling (Section 5).  Every member of a sampled group gets a
+// counter-based hash: the splitmix64 finalizer chained over (seed ^ tag, a,
+// b).  Rate sampling keeps a member when its hash is below rate * 2^64;
+// fixed-size sampling keeps the members whose hash is at most the group's
+// threshold, the cap-th smallest hash of the group (~0 when the group has at
+// most cap members), i.e. a uniform sample of exactly min(size, cap).
+//   rate, joining vertex k  tag n << 56,                 a = k, b = {u, w}
+//   ST piece of type t      tag n << 56 | (t + 1) << 48, a = k, b = {u, w}
+//                           (k-centre wedge, triangle) or u << 32 | w
+//                           (k-leaf wedge k-u-w)
+//   ST edge (size-4 join)   tag 4 << 56 | 4 << 48,       a = k, b = other end
+//   matching                tag 3 << 56 | (s + 1) << 48, a = credited vertex
+//                           (wedge centre, s = 0; smallest triangle vertex,
+//                           s = 1), b = the other two
+// where {u, w} = min << 32 | max.
+
+struct Sampling {
+    uint64_t seed = 0;
+    const uint64_t* mthr = nullptr;   // matching: per credited vertex
+    const uint64_t* kthr = nullptr;   // a join's key groups: per joining vertex
+    const uint64_t* ethr = nullptr;   // size-4 join: edge groups per joining vertex
+};
+
+__device__ __forceinline__ uint64_t unit_hash(uint64_t seed, uint64_t tag, int32_t a, uint64_t b) {
+    uint64_t h = mix64(seed ^ tag);
+    h = mix64(h ^ (uint64_t)(uint32_t)a);
+    return mix64(h ^ b);
+}
+
+__device__ __forceinline__ uint64_t pair_key(int32_t x, int32_t y) {
+    return (uint64_t)(uint32_t)min(x, y) << 32 | (uint32_t)max(x, y);
+}
+
+// Rate-sampling hash of the size-3 piece {k, u, w} joined at level n.
+__device__ __forceinline__ uint64_t sample_hash(uint64_t seed, int n, int32_t k, int32_t u,
+                                                int32_t w) {
+    return unit_hash(seed, (uint64_t)n << 56, k, pair_key(u, w));
+}
+
+__device__ __forceinline__ uint64_t piece_hash(uint64_t seed, int n, int t, int32_t k, int32_t u,
+                                               int32_t w) {
+    const uint64_t b = t == PIECE_KL ? ((uint64_t)(uint32_t)u << 32 | (uint32_t)w) : pair_key(u, w);
+    return unit_hash(seed, (uint64_t)n << 56 | (uint64_t)(t + 1) << 48, k, b);
+}
+
+__device__ __forceinline__ uint64_t edge_hash(uint64_t seed, int32_t k, int32_t o) {
+    return unit_hash(seed, 4ull << 56 | 4ull << 48, k, (uint64_t)(uint32_t)o);
+}
+
+__device__ __forceinline__ uint64_t match_hash(uint64_t seed, int s, int32_t c, int32_t x,
+                                               int32_t y) {
+    return unit_hash(seed, 3ull << 56 | (uint64_t)(s + 1) << 48, c, pair_key(x, y));
+}
+
+// The size-3 subgraphs a neighbour pair u < w of centre c stands for in
+// matching: the wedge (c; u, w), and the triangle when c < u and u ~ w
+// (credited to its smallest vertex).  Vertex-induced: the wedge only when
+// u !~ w, nothing when u, w are joined by an edge outside G_f.
+__device__ __forceinline__ void level3_units(const NbrHash& nh, const NbrHash& xh, int induced,
+                                             int32_t c, int32_t u, int32_t w, bool& wedge,
+                                             bool& tri) {
+    const bool uw = (induced || c < u) && has_edge(nh, u, w);
+    tri = c < u && uw;
+    wedge = !(induced && (uw || blocked(xh, u, w)));
+}
+
+// Piece types (bit PIECE_*) that survive matching sampling: each is the
+// matched size-3 subgraph it stands for -- the wedge centred at k (k-centre),
+// at u (k-leaf k-u-w), the triangle credited to its smallest vertex.
+__device__ __forceinline__ uint32_t matched_types(const Sampling& s, uint32_t types, int32_t k,
+                                                  int32_t u, int32_t w) {
+    if (!s.mthr || !types) return types;
+    if (((types >> PIECE_KC) & 1u) && match_hash(s.seed, 0, k, u, w) > s.mthr[k])
+        types &= ~(1u << PIECE_KC);
+    if (((types >> PIECE_KL) & 1u) && match_hash(s.seed, 0, u, k, w) > s.mthr[u])
+        types &= ~(1u << PIECE_KL);
+    if ((types >> PIECE_TR) & 1u) {
+        const int32_t c = min(k, min(u, w));
+        const int32_t x = c == k ? u : k, y = c == w ? u : w;
+        if (match_hash(s.seed, 1, c, x, y) > s.mthr[c]) types &= ~(1u << PIECE_TR);
+    }
+    return types;
+}
+
+// Piece types kept by k's key group at the size-n join under ST sampling.
+__device__ __forceinline__ uint32_t st_types(const Sampling& s, int n, uint32_t types, int32_t k,
+                                             int32_t u, int32_t w) {
+    if (!s.kthr || !types) return types;
+    const uint64_t thr = s.kthr[k];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (((types >> t) & 1u) && piece_hash(s.seed, n, t, k, u, w) > thr) types &= ~(1u << t);
+    return types;
+}
+
 struct L3Args {
     const int32_t* row;    // G_f
     const int32_t* col;
@@ -469,6 +575,8 @@ struct L3Args {
     int32_t* out;
     int64_t out_rows;
     int induced = 0;       // vertex-induced: a wedge only when u !~ w
+    NbrHash xh{nullptr, nullptr};   // vertex-induced: edges outside G_f
+    Sampling smp{};        // matching sampling (mthr) when set
 };
 
 __device__ __forceinline__ void decode_pair(int64_t r, int32_t* a, int32_t* b) {
@@ -528,8 +636,9 @@ __global__ void k_piece_fill(const int32_t* row, const int32_t* col, const int32
 // One wave per centre c; lanes over neighbour pairs u < w.  Each pair is a
 // wedge (c; u, w) stored (c, u, w); when c < u and u ~ w it is also the
 // triangle stored (c, u, w) (each triangle once, at its smallest vertex).
-// Vertex-induced mode drops the wedges whose ends are adjacent.
-// QP = (type, labels in stored order).
+// Vertex-induced mode drops the wedges whose ends are adjacent.  Matching
+// sampling keeps the subgraphs credited to c whose hash is at most c's
+// threshold.  QP = (type, labels in stored order).
 template <int MODE>
 __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
     const int lane = threadIdx.x & 63;
@@ -558,9 +667,12 @@ __global__ __launch_bounds__(TPB) void k_level3(L3Args a) {
                 w = a.col[rb + ib];
                 lu = a.vf[u];
                 lw = a.vf[w];
-                const bool uw = (a.induced || c < u) && has_edge(a.nh, u, w);
-                tri = c < u && uw;
-                wedge = !(a.induced && uw);
+                level3_units(a.nh, a.xh, a.induced, (int32_t)c, u, w, wedge, tri);
+                if (a.smp.mthr) {   // matching sampling: c's kept subgraphs
+                    const uint64_t thr = a.smp.mthr[c];
+                    if (wedge && match_hash(a.smp.seed, 0, (int32_t)c, u, w) > thr) wedge = false;
+                    if (tri && match_hash(a.smp.seed, 1, (int32_t)c, u, w) > thr) tri = false;
+                }
             }
             const uint64_t L = (uint64_t)lc | (uint64_t)lu << 6 | (uint64_t)lw << 12 | gid << 48;
             const uint64_t kw = gid << 19 | (uint64_t)lc << 12 | (uint64_t)lu << 6 | (uint64_t)lw;
@@ -638,6 +750,8 @@ struct JoinArgs {
     uint64_t sample_thr;     // keep a piece when its hash is below this
     const uint64_t* item_thr;   // or, when set, below the threshold of its work item
     int induced;             // vertex-induced: the pieces' own edges are induced, C = E_c
+    NbrHash xh;              // vertex-induced: edges outside G_f
+    Sampling smp;            // matching and ST sampling thresholds
     int64_t* counts;
     const int64_t* offsets;
     int32_t* out;
@@ -648,15 +762,31 @@ __device__ __forceinline__ bool f3_at(const uint8_t* f3, int F, int t, int a, in
     return f3[((t * F + a) * F + b) * F + c] != 0;
 }
 
-// Counter-based keep decision of a size-3 piece with vertex set {k, u, w}
-// joined at level n (subgraph sampling during joining, Section 5).
-__device__ __forceinline__ uint64_t sample_hash(uint64_t seed, int n, int32_t k, int32_t u,
-                                                int32_t w) {
-    uint64_t lo = (uint32_t)(u < w ? u : w), hi = (uint32_t)(u < w ? w : u);
-    uint64_t h = mix64(seed ^ ((uint64_t)n << 56));
-    h = mix64(h ^ (uint64_t)(uint32_t)k);
-    h = mix64(h ^ (lo << 32 | hi));
-    return h;
+// Size-3 subgraphs (bit PIECE_*) that the piece slot (k; u, w) holds among
+// the stored ones: frequent size-3 patterns (f3), matched (Section 3), and
+// in vertex-induced mode induced subgraphs of the input graph.  A k-centre
+// slot holds the wedge u-k-w and, when u ~ w, the triangle; a k-leaf slot
+// the wedge k-u-w.  `bytes` counts the adjacency probes.
+__device__ __forceinline__ uint32_t piece_types(const uint8_t* f3, int F, const NbrHash& nh,
+                                                const NbrHash& xh, int induced, bool centre,
+                                                int32_t k, int32_t u, int32_t w, int lk, int lu,
+                                                int lw, unsigned long long& bytes) {
+    uint32_t types = 0;
+    if (centre) {
+        const bool fw = f3_at(f3, F, 0, lk, lu, lw);
+        const bool ft = f3_at(f3, F, 1, lk, lu, lw);
+        bool uw = false;
+        if (ft || (induced && fw)) {
+            bytes += 8;
+            uw = has_edge(nh, u, w);
+        }
+        if (fw && !(induced && (uw || blocked(xh, u, w)))) types |= 1u << PIECE_KC;
+        if (ft && uw) types |= 1u << PIECE_TR;
+    } else if (f3_at(f3, F, 0, lu, lk, lw)) {
+        // vertex-induced: k !~ w (else it is the triangle)
+        if (!induced || (!has_edge(nh, k, w) && !blocked(xh, k, w))) types |= 1u << PIECE_KL;
+    }
+    return types;
 }
 
 // All children of one (parent, position, piece-vertex pair) candidate.
@@ -769,7 +899,11 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
             const int32_t rk = a.row[k];
             const int32_t dk = a.row[k + 1] - rk;
             const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
-            const int64_t Pk = a.npieces[k];
+            int64_t Pk = a.npieces[k];
+            // ST at the size-4 join: the parent edge must be one of the
+            // sampled edges of k's key group
+            if (N == 4 && a.smp.ethr && edge_hash(a.smp.seed, k, cv[1 - i]) > a.smp.ethr[k])
+                Pk = 0;
             if (lane == 0) {
                 cands += (unsigned long long)Pk;
                 // parent row, N(k), and the N(u) rows of the k-leaf slots
@@ -814,21 +948,9 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                     }
                     if (ok && a.sampled && sample_hash(a.seed, N, k, u, w) >= sthr) ok = false;
                     if (ok) {
-                        const int lu = a.vf[u], lw = a.vf[w];
-                        if (centre) {
-                            const bool fw = f3_at(f3, a.F, 0, lk, lu, lw);
-                            const bool ft = f3_at(f3, a.F, 1, lk, lu, lw);
-                            bool uw = false;
-                            if (ft || (a.induced && fw)) {
-                                bytes += 8;
-                                uw = has_edge(a.nh, u, w);
-                            }
-                            if (fw && !(a.induced && uw)) types |= 1u << PIECE_KC;
-                            if (ft && uw) types |= 1u << PIECE_TR;
-                        } else if (f3_at(f3, a.F, 0, lu, lk, lw)) {
-                            // vertex-induced: k !~ w (else it is the triangle)
-                            if (!a.induced || !has_edge(a.nh, k, w)) types |= 1u << PIECE_KL;
-                        }
+                        types = piece_types(f3, a.F, a.nh, a.xh, a.induced, centre, k, u, w, lk,
+                                            a.vf[u], a.vf[w], bytes);
+                        types = st_types(a.smp, N, matched_types(a.smp, types, k, u, w), k, u, w);
                     }
                 }
                 int64_t got = 0;
@@ -841,15 +963,19 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
                     cv[M] = u;
                     cv[M + 1] = w;
                     Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1));
+                    bool clear = true;   // vertex-induced: no edge outside G_f joins the sides
 #pragma unroll
                     for (int j = 0; j < M; ++j) {
                         if (j == i) continue;
                         if (has_edge(a.nh, cv[j], u)) ec |= 1u << (2 * j);
                         if (has_edge(a.nh, cv[j], w)) ec |= 1u << (2 * j + 1);
+                        if (a.induced && (blocked(a.xh, cv[j], u) || blocked(a.xh, cv[j], w)))
+                            clear = false;
                     }
                     ob = rank_bits<N>(cv);
-                    got = children<N, MODE, 0>(a, f3, cv, i, types, ec, PA, Lc, ob, pslot, lu,
-                                               lw, nullptr);
+                    if (clear)
+                        got = children<N, MODE, 0>(a, f3, cv, i, types, ec, PA, Lc, ob, pslot,
+                                                   lu, lw, nullptr);
                     bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
                 }
                 if (MODE == MODE_DOMAIN) {
@@ -878,6 +1004,150 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
         if (t) atomicAdd(a.emitted, (unsigned long long)t);
         if (cc) atomicAdd(a.cands, (unsigned long long)cc);
         if (bb) atomicAdd(a.bytes, (unsigned long long)bb);
+    }
+}
+
+// ------------------------------------------------- fixed-size group samples
+//
+// Threshold of every group of a sampled loop (Section 5): one block per
+// group, a radix select of the cap-th smallest member hash over 8-bit digits
+// from the top.  Each round recomputes the members' hashes (no member list
+// is stored) and histograms the next digit of those that share the digits
+// chosen so far; it stops at the first digit whose bin holds exactly the
+// members still needed -- every hash of that bin is kept, so the bin's upper
+// end keeps the same set as the exact cap-th hash.
+
+constexpr int SEL_TPB = 256;
+enum { SEL_PIECES = 0, SEL_EDGES = 1, SEL_MATCH = 2 };
+
+struct SelArgs {
+    const int32_t* row;      // G_f
+    const int32_t* col;
+    const int32_t* leafoff;
+    const int64_t* npieces;
+    const uint32_t* vinfo;
+    const int32_t* vg;
+    const uint8_t* f3;
+    int F;
+    NbrHash nh;
+    NbrHash xh;
+    int induced;
+    Sampling smp;            // mthr applies to the pieces' own matching
+    int n;                   // join size (pieces)
+    int64_t groups;          // vertices
+    uint64_t cap;            // members kept per group (>= 1)
+    uint64_t* thr;           // out: per group threshold
+};
+
+template <class Units>
+__device__ uint64_t block_select(int64_t slots, uint64_t cap, const Units& units,
+                                 unsigned long long* hist, uint64_t* sh) {
+    uint64_t prefix = 0, need = cap;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < slots; q += blockDim.x)
+            units(q, [&](uint64_t h) {
+                if (shift == 56 || (h >> (shift + 8)) == prefix)
+                    atomicAdd(&hist[(h >> shift) & 255u], 1ull);
+            });
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t done = 0, res = 0;
+            if (shift == 56) {
+                uint64_t total = 0;
+                for (int b = 0; b < 256; ++b) total += hist[b];
+                if (total <= cap) {
+                    done = 1;
+                    res = ~0ull;
+                }
+            }
+            if (!done) {
+                uint64_t below = 0;
+                int b = 0;
+                for (; b < 255; ++b) {
+                    if (below + hist[b] >= need) break;
+                    below += hist[b];
+                }
+                need -= below;
+                prefix = prefix << 8 | (uint64_t)b;
+                if (hist[b] == need || shift == 0) {
+                    done = 1;
+                    res = shift == 0 ? prefix : (prefix << shift | ((1ull << shift) - 1));
+                }
+            }
+            sh[0] = done;
+            sh[1] = res;
+            sh[2] = prefix;
+            sh[3] = need;
+        }
+        __syncthreads();
+        const uint64_t done = sh[0], res = sh[1];
+        prefix = sh[2];
+        need = sh[3];
+        __syncthreads();
+        if (done) return res;
+    }
+    return ~0ull;
+}
+
+// KIND SEL_PIECES: group = joining vertex k, members = the stored size-3
+// subgraphs containing k (piece slots x their types) at the size-n join;
+// SEL_EDGES: members = k's G_f edges (size-4 join); SEL_MATCH: group =
+// vertex c, members = the size-3 subgraphs credited to c in matching.
+template <int KIND>
+__global__ __launch_bounds__(SEL_TPB) void k_group_select(SelArgs a) {
+    __shared__ unsigned long long hist[256];
+    __shared__ uint64_t sh[4];
+    for (int64_t k = blockIdx.x; k < a.groups; k += gridDim.x) {
+        const int32_t rk = a.row[k], dk = a.row[k + 1] - rk;
+        const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
+        int64_t slots = 0, most = 0;   // slots, and an upper bound on members
+        if (KIND == SEL_PIECES) {
+            slots = a.npieces[k];
+            most = slots + ncen;
+        } else if (KIND == SEL_EDGES) {
+            slots = most = dk;
+        } else {
+            slots = ncen;
+            most = 2 * ncen;
+        }
+        uint64_t res = ~0ull;
+        if ((uint64_t)most > a.cap) {   // block-uniform
+            const int32_t kk = (int32_t)k;
+            if (KIND == SEL_PIECES) {
+                const int lk = (int)(a.vinfo[k] >> 26);
+                const uint8_t* f3 = a.f3 + (size_t)a.vg[k] * 2 * a.F * a.F * a.F;
+                res = block_select(slots, a.cap, [&](int64_t q, auto&& emit) {
+                    int32_t u, w;
+                    const bool centre = piece_at(a.row, a.col, a.leafoff, rk, dk, ncen, q, u, w);
+                    if (w == kk) return;
+                    unsigned long long by = 0;
+                    uint32_t types = piece_types(f3, a.F, a.nh, a.xh, a.induced, centre, kk, u, w,
+                                                 lk, (int)(a.vinfo[u] >> 26),
+                                                 (int)(a.vinfo[w] >> 26), by);
+                    types = matched_types(a.smp, types, kk, u, w);
+                    for (int t = 0; t < 3; ++t)
+                        if ((types >> t) & 1u) emit(piece_hash(a.smp.seed, a.n, t, kk, u, w));
+                }, hist, sh);
+            } else if (KIND == SEL_EDGES) {
+                res = block_select(slots, a.cap, [&](int64_t q, auto&& emit) {
+                    emit(edge_hash(a.smp.seed, kk, a.col[rk + q]));
+                }, hist, sh);
+            } else {
+                res = block_select(slots, a.cap, [&](int64_t q, auto&& emit) {
+                    int32_t ia, ib;
+                    decode_pair(q, &ia, &ib);
+                    const int32_t u = a.col[rk + ia], w = a.col[rk + ib];
+                    bool wedge, tri;
+                    level3_units(a.nh, a.xh, a.induced, kk, u, w, wedge, tri);
+                    if (wedge) emit(match_hash(a.smp.seed, 0, kk, u, w));
+                    if (tri) emit(match_hash(a.smp.seed, 1, kk, u, w));
+                }, hist, sh);
+            }
+        }
+        if (threadIdx.x == 0) a.thr[k] = res;
+        __syncthreads();
     }
 }
 
@@ -1022,6 +1292,8 @@ struct TileArgs {
     uint64_t sample_thr;
     const uint64_t* item_thr;   // per work item sampling thresholds, or null
     int induced;                // vertex-induced: induced pieces, C = E_c only
+    NbrHash xh;                 // vertex-induced: edges outside G_f
+    Sampling smp;               // matching and ST sampling thresholds
 };
 
 constexpr uint32_t RANK_MASK = (1u << 26) - 1;
@@ -1084,7 +1356,7 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
 // adjacency with vertices in id order (the rule depends on nothing else);
 // the connecting-edge subsets that the Section 4.5 pruning rejects are
 // excluded from the enumeration up front.
-template <int N>
+template <int N, bool EXTRA>
 __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f3,
                                              const int32_t (&cv)[N],
                                              const int32_t (&lr)[N], int i, uint32_t types,
@@ -1148,7 +1420,7 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
             rpar | eku | (t == PIECE_KC ? ekw : (t == PIECE_KL ? euw : (ekw | euw)));
         const uint32_t allowed = t == PIECE_KL ? allow_kl : allow_both;
         // vertex-induced: the one child keeps every connecting edge
-        if (a.induced && allowed != ec) continue;
+        if (EXTRA && a.induced && allowed != ec) continue;
         const uint64_t kbase = (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)t << 30 |
                                (uint64_t)lu << 24 | (uint64_t)lw << 18;
         uint32_t sub = allowed;
@@ -1201,7 +1473,7 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                 }
                 ++got;
             }
-            if (!sub || a.induced) break;
+            if (!sub || (EXTRA && a.induced)) break;
             sub = (sub - 1) & allowed;
         }
     }
@@ -1210,7 +1482,9 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
 
 // At most 128 VGPRs (4 waves per SIMD): the occupancy hides the latency of
 // the adjacency probes and bitmap reads better than the extra registers.
-template <int N>
+// EXTRA = false builds the exact edge-induced join without the sampling and
+// vertex-induced paths (fewer live registers).
+template <int N, bool EXTRA>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles(
     TileArgs a) {
     constexpr int M = N - 2;
@@ -1276,7 +1550,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             }
             bytes += 4;
             bool ok = w != k;
-            if (ok && a.sampled) {
+            if (ok && EXTRA && a.sampled) {
                 hsh = sample_hash(a.seed, N, k, u, w);
                 if (!a.item_thr && hsh >= a.sample_thr) ok = false;
             }
@@ -1286,20 +1560,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 lw = (int)(iw >> 26);
                 lru = (int32_t)(iu & RANK_MASK);
                 lrw = (int32_t)(iw & RANK_MASK);
-                if (centre) {
-                    const bool fw = f3_at(f3, a.F, 0, lk, lu, lw);
-                    const bool ft = f3_at(f3, a.F, 1, lk, lu, lw);
-                    bool uw = false;
-                    if (ft || (a.induced && fw)) {
-                        bytes += 8;
-                        uw = has_edge(a.nh, u, w);
-                    }
-                    if (fw && !(a.induced && uw)) types |= 1u << PIECE_KC;
-                    if (ft && uw) types |= 1u << PIECE_TR;
-                } else if (f3_at(f3, a.F, 0, lu, lk, lw)) {
-                    // vertex-induced: k !~ w (else it is the triangle)
-                    if (!a.induced || !has_edge(a.nh, k, w)) types |= 1u << PIECE_KL;
-                }
+                types = piece_types(f3, a.F, a.nh, a.xh, EXTRA && a.induced, centre, k, u, w, lk, lu, lw,
+                                    bytes);
+                if (EXTRA) types = st_types(a.smp, N, matched_types(a.smp, types, k, u, w), k, u, w);
             }
         }
         const int32_t qmin = min(k, min(u, w));
@@ -1341,6 +1604,10 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             bool ok = types != 0;
 #pragma unroll
             for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
+            // ST at the size-4 join: the parent edge must be one of the
+            // sampled edges of k's key group (wave-uniform)
+            if (EXTRA && N == 4 && a.smp.ethr && edge_hash(a.smp.seed, k, cv[1 - i]) > a.smp.ethr[k])
+                ok = false;
             // n = 4: the smallest vertex of every child lies in the accepted
             // size-3 part (exhaustively true for connected graphs on 4
             // vertices), so a piece above min(parent \ k) is rejected; n = 5:
@@ -1357,18 +1624,22 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     if (!lex_less3(q0, q1, q2, p0, p1, p2)) ok = false;
                 }
             }
-            if (ok && a.item_thr && hsh >= a.item_thr[(int64_t)pslot * M + i]) ok = false;
+            if (EXTRA && ok && a.item_thr && hsh >= a.item_thr[(int64_t)pslot * M + i]) ok = false;
             int got = 0;
             if (ok) {
                 const uint64_t PA = a.padj[pslot];
                 cv[M] = u;
                 cv[M + 1] = w;
                 const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
+                // vertex-induced: an edge outside G_f between the two sides
+                // leaves no child (of this parent; the piece stays for others)
+                const uint32_t ty =
+                    (EXTRA && a.induced && a.xh.off && connecting_edges<N>(a.xh, cv, i)) ? 0u : types;
                 const uint64_t Lc =
                     L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
                 lr[M] = lru;
                 lr[M + 1] = lrw;
-                got = children_tile<N>(a, f3, cv, lr, i, types, ec, PA, Lc, pslot, lu, lw, c);
+                got = children_tile<N, EXTRA>(a, f3, cv, lr, i, ty, ec, PA, Lc, pslot, lu, lw, c);
                 emit += (unsigned long long)got;
                 bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
             }
@@ -1898,6 +2169,20 @@ struct Miner {
     DBuf<uint32_t> nhoff;
     DBuf<int32_t> nhtab;
     NbrHash nh() const { return NbrHash{nhoff.p, nhtab.p}; }
+    // vertex-induced mode: tables of the edges outside G_f (empty: none)
+    DBuf<uint32_t> xhoff;
+    DBuf<int32_t> xhtab;
+    NbrHash xh() const { return NbrHash{xhoff.p, xhtab.p}; }
+    DBuf<uint64_t> mthr;            // matching sampling thresholds
+    Sampling sampling() const {
+        Sampling s;
+        s.seed = opt.seed;
+        s.mthr = mthr.p;
+        return s;
+    }
+    void group_thresholds(int kind, int n, uint64_t cap, DBuf<uint64_t>& thr);
+    void neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
+                          DBuf<int32_t>& tab);
     DBuf<int64_t> npieces;
     DBuf<int32_t> leafoff;
     DBuf<uint8_t> f3;
@@ -2176,28 +2461,31 @@ void Miner::build_gf() {
     to_device(df2.p, f2.data(), f2.size());
     const int64_t n = g->n;
     DBuf<int64_t> cnt((size_t)n + 1);
-    k_gf_count<<<grid_for(n, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F, cnt.p);
+    k_gf_count<<<grid_for(n, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F, 1,
+                                                  cnt.p);
     FSM_LAUNCH_CHECK();
     fnnz = scan_exclusive(cnt.p, cnt.p, n);
     frow.alloc((size_t)n + 1);
     fcol.alloc((size_t)(fnnz > 0 ? fnnz : 1));
-    k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F,
+    k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F, 1,
                                                      cnt.p, fnnz, frow.p, fcol.p);
     FSM_LAUNCH_CHECK();
     // per-vertex neighbour hash tables (load <= 1/2) and piece counts
-    {
-        DBuf<int64_t> cap((size_t)n + 1);
-        k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(frow.p, n, cap.p);
+    neighbour_tables(frow.p, fcol.p, nhoff, nhtab);
+    if (opt.mode & FSM_INDUCED) {
+        // the graph edges between frequent-label vertices outside G_f
+        k_gf_count<<<grid_for(n, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n, df2.p, F,
+                                                      0, cnt.p);
         FSM_LAUNCH_CHECK();
-        const int64_t total = scan_exclusive(cap.p, cap.p, n);
-        if (total >= (int64_t)UINT32_MAX)
-            fail(FSM_EUNSUPPORTED, "neighbour tables exceed 2^32 slots");
-        nhoff.alloc((size_t)n + 1);
-        nhtab.alloc((size_t)(total > 0 ? total : 1));
-        k_nbr_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(frow.p, fcol.p, n, cap.p, total, nhoff.p,
-                                                         nhtab.p);
-        FSM_LAUNCH_CHECK();
-        FSM_HIP(hipStreamSynchronize(st));
+        const int64_t xnnz = scan_exclusive(cnt.p, cnt.p, n);
+        if (xnnz > 0) {
+            DBuf<int32_t> xrow((size_t)n + 1), xcol((size_t)xnnz);
+            k_gf_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(g->row, g->col, vf.p, g->vg, n,
+                                                             df2.p, F, 0, cnt.p, xnnz, xrow.p,
+                                                             xcol.p);
+            FSM_LAUNCH_CHECK();
+            neighbour_tables(xrow.p, xcol.p, xhoff, xhtab);
+        }
     }
     npieces.alloc((size_t)n);
     leafoff.alloc((size_t)(fnnz > 0 ? fnnz : 1));
@@ -2206,13 +2494,55 @@ void Miner::build_gf() {
     for (fsm_result* r : res) r->stats.filtered_edges = fnnz / 2;
 }
 
+// Per-vertex linear-probing neighbour tables of the CSR (row, col).
+void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
+                             DBuf<int32_t>& tab) {
+    const int64_t n = g->n;
+    DBuf<int64_t> cap((size_t)n + 1);
+    k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(row, n, cap.p);
+    FSM_LAUNCH_CHECK();
+    const int64_t total = scan_exclusive(cap.p, cap.p, n);
+    if (total >= (int64_t)UINT32_MAX) fail(FSM_EUNSUPPORTED, "neighbour tables exceed 2^32 slots");
+    off.alloc((size_t)n + 1);
+    tab.alloc((size_t)(total > 0 ? total : 1));
+    k_nbr_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(row, col, n, cap.p, total, off.p, tab.p);
+    FSM_LAUNCH_CHECK();
+    FSM_HIP(hipStreamSynchronize(st));
+}
+
+// Thresholds of every vertex's group of a fixed-size sample (Section 5):
+// kind SEL_MATCH (size-3 subgraphs credited to the vertex), SEL_PIECES
+// (stored size-3 subgraphs containing the joining vertex, size-n join) or
+// SEL_EDGES (its G_f edges, size-4 join); cap members per group.
+void Miner::group_thresholds(int kind, int n, uint64_t cap, DBuf<uint64_t>& thr) {
+    thr.alloc((size_t)g->n);
+    SelArgs a;
+    a.row = frow.p; a.col = fcol.p; a.leafoff = leafoff.p; a.npieces = npieces.p;
+    a.vinfo = vinfo.p; a.vg = g->vg; a.f3 = f3.p; a.F = F;
+    a.nh = nh(); a.xh = xh();
+    a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+    a.smp = sampling();
+    a.n = n; a.groups = g->n; a.cap = cap; a.thr = thr.p;
+    const unsigned grid = grid_for(g->n, 1, 1u << 16);
+    switch (kind) {
+        case SEL_PIECES: k_group_select<SEL_PIECES><<<grid, SEL_TPB, 0, st>>>(a); break;
+        case SEL_EDGES: k_group_select<SEL_EDGES><<<grid, SEL_TPB, 0, st>>>(a); break;
+        default: k_group_select<SEL_MATCH><<<grid, SEL_TPB, 0, st>>>(a); break;
+    }
+    FSM_LAUNCH_CHECK();
+}
+
 void Miner::level3() {
     Level& L = lv[3];
     L.n = 3;
+    // matching sampling: t subgraphs kept per credited vertex (Section 5)
+    if (opt.match_threshold > 0) group_thresholds(SEL_MATCH, 3, (uint64_t)opt.match_threshold, mthr);
     auto launch = [&](Rec R, int) {
         L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), R, counters.p,
                  nullptr, nullptr, nullptr, 0};
         a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+        a.xh = xh();
+        a.smp = sampling();
         k_level3<MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a);
         FSM_LAUNCH_CHECK();
     };
@@ -2499,6 +2829,19 @@ void Miner::join(int n) {
     const uint64_t thr =
         opt.sampling_rate >= 1.0 ? ~0ull
                                  : (uint64_t)std::ldexp(opt.sampling_rate, 64);
+    // ST x (Section 5): x^2 size-3 subgraphs per key group at every join,
+    // and x edges per key group at the size-4 join
+    Sampling smp = sampling();
+    DBuf<uint64_t> kthr, ethr;
+    if (opt.join_threshold > 0 && nwork > 0) {
+        const uint64_t x = (uint64_t)opt.join_threshold;
+        group_thresholds(SEL_PIECES, n, x * x, kthr);
+        smp.kthr = kthr.p;
+        if (n == 4) {
+            group_thresholds(SEL_EDGES, n, x, ethr);
+            smp.ethr = ethr.p;
+        }
+    }
     auto args = [&](Rec R, int64_t* counts, const int64_t* offsets, int32_t* out, int64_t rows) {
         JoinArgs a;
         a.row = frow.p; a.col = fcol.p; a.vf = vf.p;
@@ -2514,6 +2857,8 @@ void Miner::join(int n) {
         a.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
         a.seed = opt.seed; a.sample_thr = thr; a.item_thr = ithr.p;
         a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+        a.xh = xh();
+        a.smp = smp;
         a.counts = counts; a.offsets = offsets; a.out = out; a.out_rows = rows;
         return a;
     };
@@ -2571,9 +2916,15 @@ void Miner::join(int n) {
         t.sampled = (opt.mode & FSM_SAMPLED) ? 1 : 0;
         t.seed = opt.seed; t.sample_thr = thr; t.item_thr = ithr.p;
         t.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+        t.xh = xh();
+        t.smp = smp;
         t.dtab = dtab.p;
         return t;
     };
+    // the plain exact join runs a build of the tile kernel without the
+    // sampling and vertex-induced paths
+    const bool extra = (opt.mode & (FSM_SAMPLED | FSM_INDUCED)) || ithr.p || smp.kthr ||
+                       smp.ethr || smp.mthr;
     hipEvent_t j0, j1;
     FSM_HIP(hipEventCreate(&j0));
     FSM_HIP(hipEventCreate(&j1));
@@ -2591,13 +2942,19 @@ void Miner::join(int n) {
             if (G.ntiles > 0) {
                 TileArgs t = tile_args(R);
                 t.item_children = pass == 0 ? ich.p : nullptr;
+#define FSM_TILES_CASE(NN)                                                          \
+    case NN:                                                                        \
+        if (extra) k_join_tiles<NN, true><<<grid_persistent, TPB, 0, st>>>(t);       \
+        else k_join_tiles<NN, false><<<grid_persistent, TPB, 0, st>>>(t);            \
+        break;
                 switch (n) {
-                    case 4: k_join_tiles<4><<<grid_persistent, TPB, 0, st>>>(t); break;
-                    case 5: k_join_tiles<5><<<grid_persistent, TPB, 0, st>>>(t); break;
-                    case 6: k_join_tiles<6><<<grid_persistent, TPB, 0, st>>>(t); break;
-                    case 7: k_join_tiles<7><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    FSM_TILES_CASE(4)
+                    FSM_TILES_CASE(5)
+                    FSM_TILES_CASE(6)
+                    FSM_TILES_CASE(7)
                     default: fail(FSM_EINVAL, "bad join size %d", n);
                 }
+#undef FSM_TILES_CASE
                 FSM_LAUNCH_CHECK();
             }
             FSM_HIP(hipEventRecord(j1, st));
@@ -2774,6 +3131,8 @@ void Miner::run() {
                 L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), rec(L), counters.p,
                          counts, offsets, out, rows};
                 a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+                a.xh = xh();
+                a.smp = sampling();
                 if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
                 else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
                 FSM_LAUNCH_CHECK();
