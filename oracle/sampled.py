@@ -1,4 +1,5 @@
-"""Two-vertex joins with subgraph sampling, subgraph by subgraph, on tiny
+"""Two-vertex joins with subgraph sampling, and the single-vertex exploration
+they are compared with (``mine_single``), subgraph by subgraph, on tiny
 graphs -- TEST INFRASTRUCTURE ONLY.
 
 Only ``tests/`` may import this module; the device library never calls it.
@@ -52,7 +53,8 @@ implement from its published definition, with these keys:
   ST piece        tag n << 56 | (type + 1) << 48, a = k, b = {u, w} sorted
                   (k-centre wedge, triangle) or u << 32 | w (k-leaf wedge
                   k-u-w; type 0 k-centre, 1 k-leaf, 2 triangle)
-  ST edge         tag 4 << 56 | 4 << 48,          a = k, b = other end
+  ST edge         tag n << 56 | 4 << 48,          a = k, b = other end
+                  (size-4 two-vertex join; every single-vertex join n)
   matching        tag 3 << 56 | (s + 1) << 48,    a = credited vertex,
                   b = other two sorted (s = 0 wedge, 1 triangle)
 where {u, w} sorted means min << 32 | max.
@@ -99,8 +101,8 @@ def piece_hash(seed, n, k, t, u, w):
     return unit_hash(seed, n << 56 | (t + 1) << 48, k, b)
 
 
-def edge_hash(seed, k, o):
-    return unit_hash(seed, 4 << 56 | 4 << 48, k, o)
+def edge_hash(seed, k, o, n=4):
+    return unit_hash(seed, n << 56 | 4 << 48, k, o)
 
 
 def match_hash(seed, s, c, a, b):
@@ -345,6 +347,71 @@ def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_thr
                                 ok = False
                 if not ok:
                     continue
+            produced.append(S)
+        levels[size] = _Level(produced, labels, support)
+        counts[size] = len(produced)
+    out = []
+    for size, L in levels.items():
+        for (labs, bits) in L.frequent:
+            adjbits = sum(1 << i for i, b in enumerate(bits) if b)
+            out.append(((size, labs, bits), (size, labs, adjbits, L.support[(labs, bits)])))
+    out.sort(key=lambda x: x[0])
+    res = [x[1] for x in out]
+    return (res, counts) if with_counts else res
+
+
+# ------------------------------------------------ single-vertex exploration
+
+def removal(S):
+    """(v, k) of the single-vertex join's rule: v is the largest vertex
+    whose removal leaves S connected, k its smallest neighbour in S."""
+    verts, edges = S
+    for v in sorted(verts, reverse=True):
+        rest = verts - {v}
+        if _connected(rest, _on(S, rest)[1]):
+            nb = [a if b == v else b for a, b in edges if v in (a, b)]
+            return v, min(nb)
+    return None
+
+
+def mine_single(n_vertices, src, dst, labels, support, max_size, *, join_threshold=0,
+                seed=0, induced=False, with_counts=False):
+    """Single-vertex exploration (the baseline of Section 6): every size-n
+    subgraph S is the size-(n-1) subgraph S - v joined with the edge (k, v)
+    of the removal rule (v, k) above, plus the other edges of v into S - v.
+    S is produced iff S - v is stored at size n-1 and, with sampling
+    threshold x, the edge (k, v) is one of the x sampled G_f edges of k's
+    neighbour list at this join (Section 6.3's ST for single-vertex
+    exploration).  Stored and reported as in ``mine``; no pruning (the
+    single-vertex join has no size-3 table)."""
+    n = int(n_vertices)
+    labels = [int(x) for x in labels]
+    edges = _normalize(src, dst)
+    gadj = {v: set() for v in range(n)}
+    for a, b in edges:
+        gadj[a].add(b)
+        gadj[b].add(a)
+    L2 = _Level([(frozenset(e), frozenset([e])) for e in edges], labels, support)
+    adj = {v: set() for v in range(n)}
+    for a, b in edges:
+        if L2.code[(frozenset((a, b)), frozenset([(a, b)]))] in L2.frequent:
+            adj[a].add(b)
+            adj[b].add(a)
+    levels = {2: L2}
+    counts = {}
+    for size in range(3, max_size + 1):
+        ethr = {}
+        if join_threshold > 0:
+            ethr = {k: threshold([edge_hash(seed, k, o, size) for o in adj[k]], join_threshold)
+                    for k in range(n) if adj[k]}
+        parents = levels[size - 1].stored
+        produced = []
+        for S in _subgraphs(adj, gadj, n, size, induced):
+            v, k = removal(S)
+            if _on(S, S[0] - {v}) not in parents:
+                continue
+            if join_threshold > 0 and edge_hash(seed, k, v, size) > ethr[k]:
+                continue
             produced.append(S)
         levels[size] = _Level(produced, labels, support)
         counts[size] = len(produced)

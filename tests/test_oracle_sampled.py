@@ -158,3 +158,72 @@ def test_rate_one_is_exact_and_rate_sampling_is_a_lower_bound():
     got = as_map(sp.mine(16, src, dst, lab, 2, 5, rate=0.3, seed=3))
     assert all(k in exact and s <= exact[k] for k, s in got.items())
     assert got != exact
+
+
+# ------------------------------------------------ single-vertex exploration
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("induced", [False, True])
+def test_single_vertex_unsampled_equals_exact_miner(seed, induced):
+    src, dst, lab = graph(seed, 16, 30, 2 + seed % 3)
+    for t in (2, 3):
+        want = oracle.mine(16, src, dst, lab, t, 5, induced=induced)
+        assert sp.mine_single(16, src, dst, lab, t, 5, induced=induced) == want
+
+
+@pytest.mark.parametrize("induced", [False, True])
+def test_single_vertex_produces_every_subgraph_once(induced):
+    src, dst, lab = graph(9, 11, 16, 1)
+    _, counts = sp.mine_single(11, src, dst, lab, 1, 5, with_counts=True, induced=induced)
+    _, want = brute.mine(11, src, dst, lab, 1, 5, with_counts=True, induced=induced)
+    assert all(counts[k] == want[k] for k in (3, 4, 5))
+
+
+def test_single_vertex_removal_rule():
+    # path 0-1-2-3: removing 3 keeps it connected, its neighbour is 2;
+    # star centred at 3 with leaves 0, 1, 2: 3 is a cut vertex, so v = 2, k = 3
+    path = (frozenset(range(4)), frozenset([(0, 1), (1, 2), (2, 3)]))
+    assert sp.removal(path) == (3, 2)
+    star = (frozenset(range(4)), frozenset([(0, 3), (1, 3), (2, 3)]))
+    assert sp.removal(star) == (2, 3)
+    cyc = (frozenset(range(4)), frozenset([(0, 1), (1, 2), (2, 3), (0, 3)]))
+    assert sp.removal(cyc) == (3, 0)
+
+
+def test_single_vertex_path_closed_form():
+    # path 0-1-...-9, one label, t = 1: the size-n subgraphs are the 11 - n
+    # subpaths; subpath a..a+n-1 removes its end a+n-1 with key a+n-2, so it
+    # is produced iff every prefix subpath is, and each step's edge
+    # (a+j-1, a+j) is among the x sampled edges of a+j-1 (x >= 2 keeps all)
+    src = np.arange(9, dtype=np.int32)
+    dst = np.arange(1, 10, dtype=np.int32)
+    lab = np.zeros(10, np.int32)
+    for seed in (0, 3, 8):
+        _, counts = sp.mine_single(10, src, dst, lab, 1, 5, join_threshold=1, seed=seed,
+                                   with_counts=True)
+        adj = {v: [u for u in (v - 1, v + 1) if 0 <= u <= 9] for v in range(10)}
+
+        def kept(k, o, size):
+            h = {u: sp.edge_hash(seed, k, u, size) for u in adj[k]}
+            return h[o] <= sp.threshold(list(h.values()), 1)
+        for size in (3, 4, 5):
+            want = sum(all(kept(a + j - 1, a + j, j + 1) for j in range(2, size))
+                       for a in range(11 - size))
+            assert counts[size] == want, (seed, size)
+        _, full = sp.mine_single(10, src, dst, lab, 1, 5, join_threshold=2, seed=seed,
+                                 with_counts=True)
+        assert full == {3: 8, 4: 7, 5: 6}
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_single_vertex_sampling_is_a_nested_lower_bound(seed):
+    src, dst, lab = graph(80 + seed, 16, 32, 2)
+    exact = as_map(oracle.mine(16, src, dst, lab, 2, 5))
+    prev = None
+    for x in (1, 2, 3):
+        got = as_map(sp.mine_single(16, src, dst, lab, 2, 5, join_threshold=x, seed=seed))
+        assert all(k in exact and s <= exact[k] for k, s in got.items())
+        if prev is not None:
+            assert all(k in got and s <= got[k] for k, s in prev.items())
+        prev = got
+    assert as_map(sp.mine_single(16, src, dst, lab, 2, 5, join_threshold=64, seed=seed)) == exact
