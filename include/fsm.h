@@ -72,9 +72,15 @@ enum {
     FSM_BATCHED = 1,  /* many graphs in one pass (fsm_mine_batch) */
     FSM_LEARNED = 2,  /* size join tables from a cost model (options.model) */
     FSM_SAMPLED = 4,  /* subgraph sampling during joining (Section 5) */
-    FSM_INDUCED = 8   /* vertex-induced subgraphs: embeddings must also map
+    FSM_INDUCED = 8,  /* vertex-induced subgraphs: embeddings must also map
                          pattern non-edges onto non-edges (a join keeps every
                          connecting edge, C = E_c, Section 4.2) */
+    FSM_SINGLE = 16   /* single-vertex exploration, the baseline of Section
+                         6: every size n >= 3 joins the size-(n-1) subgraphs
+                         with one edge (no size-3 table, no pruning).  Same
+                         results; join_threshold x then keeps x edges of
+                         every neighbour list per join.  Not with
+                         FSM_SAMPLED, FSM_LEARNED or match_threshold */
 };
 
 /* Join tile schedules (fsm_options.schedule).  Results never depend on it. */
@@ -122,6 +128,14 @@ typedef struct {
     int64_t rank_slices;      /* domain passes over vertex-rank slices: 1
                                  when the domain bitmaps of the level fit
                                  the pool budget at once */
+    int64_t hash_bytes;       /* join levels: bytes the join's loops read
+                                 from the subgraph lists grouped by joining
+                                 vertex, every read a miss (the accounting of
+                                 Section 6.2's memory-access comparison), 4
+                                 per vertex id: per work item, 12 per stored
+                                 size-3 subgraph containing its joining
+                                 vertex (two-vertex) or 8 per G_f edge of it
+                                 (single-vertex), at most the ST sample */
 } fsm_level_stats;
 
 typedef struct {
@@ -146,7 +160,7 @@ typedef struct {
     int64_t support;          /* MNI threshold t >= 1 */
     int32_t max_size;         /* 2..7 */
     uint32_t mode;            /* FSM_PLAIN, or any of FSM_SAMPLED,
-                                 FSM_LEARNED, FSM_INDUCED */
+                                 FSM_LEARNED, FSM_INDUCED, FSM_SINGLE */
     int32_t disable_pruning;  /* 1: skip the Section 4.5 pruning (results
                                  are identical; counters differ) */
     int32_t schedule;         /* join tile schedule: FSM_SCHEDULE_QUEUE
@@ -218,7 +232,8 @@ int64_t fsm_graph_edges(const fsm_graph *g);
  * aggregation).
  *   support    MNI threshold t (>= 1); a pattern is kept iff sigma >= t
  *   max_size   2..7
- *   mode       FSM_PLAIN or FSM_INDUCED (FSM_SAMPLED needs fsm_mine_ex)
+ *   mode       FSM_PLAIN, or FSM_INDUCED and/or FSM_SINGLE (FSM_SAMPLED needs
+ *              fsm_mine_ex)
  *   out        receives the result handle
  * Errors: FSM_EINVAL (NULL graph/out, support < 1, max_size outside 2..7,
  * unknown mode bits, FSM_SAMPLED here); FSM_EUNSUPPORTED when more than

@@ -26,6 +26,7 @@ FSM_BATCHED = 1
 FSM_LEARNED = 2
 FSM_SAMPLED = 4
 FSM_INDUCED = 8
+FSM_SINGLE = 16
 FSM_SCHEDULE_QUEUE = 0
 FSM_SCHEDULE_STATIC = 1
 FEATURE_LABELS = 16
@@ -55,7 +56,8 @@ class LevelStats(ctypes.Structure):
                 ("algorithmic_bytes", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
                 ("domain_passes", ctypes.c_int64), ("qp_capacity", ctypes.c_int64),
-                ("qp_predicted", ctypes.c_int64), ("rank_slices", ctypes.c_int64)]
+                ("qp_predicted", ctypes.c_int64), ("rank_slices", ctypes.c_int64),
+                ("hash_bytes", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

@@ -147,8 +147,12 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
         if (opt->support < 1) fail(FSM_EINVAL, "fsm_mine: support must be >= 1");
         if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
             fail(FSM_EINVAL, "fsm_mine: max_size must be in [2, %d]", FSM_MAX_SIZE);
-        if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED | FSM_INDUCED))
+        if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED | FSM_INDUCED | FSM_SINGLE))
             fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
+        if ((opt->mode & FSM_SINGLE) &&
+            ((opt->mode & (FSM_SAMPLED | FSM_LEARNED)) || opt->match_threshold > 0))
+            fail(FSM_EINVAL, "fsm_mine: FSM_SINGLE excludes FSM_SAMPLED, FSM_LEARNED and "
+                             "match_threshold");
         if ((opt->mode & FSM_LEARNED) && !opt->model)
             fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
         if (opt->schedule != FSM_SCHEDULE_QUEUE && opt->schedule != FSM_SCHEDULE_STATIC)

@@ -476,7 +476,8 @@ __global__ __launch_bounds__(TPB) void k_level2(L2Args a) {
 //   ST piece of type t      tag n << 56 | (t + 1) << 48, a = k, b = {u, w}
 //                           (k-centre wedge, triangle) or u << 32 | w
 //                           (k-leaf wedge k-u-w)
-//   ST edge (size-4 join)   tag 4 << 56 | 4 << 48,       a = k, b = other end
+//   ST edge of a size-n join  tag n << 56 | 4 << 48,     a = k, b = other end
+//                           (two-vertex n = 4; every single-vertex join)
 //   matching                tag 3 << 56 | (s + 1) << 48, a = credited vertex
 //                           (wedge centre, s = 0; smallest triangle vertex,
 //                           s = 1), b = the other two
@@ -511,8 +512,8 @@ __device__ __forceinline__ uint64_t piece_hash(uint64_t seed, int n, int t, int3
     return unit_hash(seed, (uint64_t)n << 56 | (uint64_t)(t + 1) << 48, k, b);
 }
 
-__device__ __forceinline__ uint64_t edge_hash(uint64_t seed, int32_t k, int32_t o) {
-    return unit_hash(seed, 4ull << 56 | 4ull << 48, k, (uint64_t)(uint32_t)o);
+__device__ __forceinline__ uint64_t edge_hash(uint64_t seed, int n, int32_t k, int32_t o) {
+    return unit_hash(seed, (uint64_t)n << 56 | 4ull << 48, k, (uint64_t)(uint32_t)o);
 }
 
 __device__ __forceinline__ uint64_t match_hash(uint64_t seed, int s, int32_t c, int32_t x,
@@ -902,7 +903,7 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
             int64_t Pk = a.npieces[k];
             // ST at the size-4 join: the parent edge must be one of the
             // sampled edges of k's key group
-            if (N == 4 && a.smp.ethr && edge_hash(a.smp.seed, k, cv[1 - i]) > a.smp.ethr[k])
+            if (N == 4 && a.smp.ethr && edge_hash(a.smp.seed, 4, k, cv[1 - i]) > a.smp.ethr[k])
                 Pk = 0;
             if (lane == 0) {
                 cands += (unsigned long long)Pk;
@@ -1007,6 +1008,232 @@ __global__ __launch_bounds__(TPB) void k_join(JoinArgs a) {
     }
 }
 
+// Rank-space pair bit: vertices ordered by id, pair (a, b) of ranks in the
+// row-major upper-triangle order of an N-vertex graph.
+template <int N>
+__device__ __forceinline__ uint32_t rbit(int a, int b) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return 1u << (lo * N - lo * (lo + 1) / 2 + (hi - lo - 1));
+}
+
+// ------------------------------------------ single-vertex exploration
+//
+// The baseline that two-vertex exploration is compared with (Section 6):
+// a size-n subgraph is a size-(n-1) parent plus one vertex u joined to the
+// parent's vertex k by an edge, with any subset of u's other edges into the
+// parent (all of them when vertex-induced).  Each subgraph is produced once:
+// u must be its largest vertex whose removal leaves it connected, k the
+// smallest neighbour of u.  That rule depends only on the child's adjacency
+// in id order, so it is a table (svtab): entry = rank(u) | rank(k) << 4,
+// 0xff for a disconnected adjacency.
+
+__global__ void k_single_table(int n, uint8_t* tab) {
+    const uint32_t total = 1u << (n * (n - 1) / 2);
+    const uint32_t all = (1u << n) - 1u;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += gridDim.x * blockDim.x) {
+        uint64_t A = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if ((x >> pair_pos(i, j, n)) & 1u) A = add_edge(A, i, j);
+        uint8_t e = 0xff;
+        if (connected(all, A, n))
+            for (int v = n - 1; v >= 0; --v)
+                if (connected(all & ~(1u << v), A, n)) {
+                    e = (uint8_t)(v | (__ffs(amask(A, v)) - 1) << 4);
+                    break;
+                }
+        tab[x] = e;
+    }
+}
+
+struct SingleArgs {
+    const int32_t* row;      // G_f
+    const int32_t* col;
+    const int32_t* vf;
+    const int32_t* vg;       // graph of each vertex
+    NbrHash nh;
+    NbrHash xh;              // vertex-induced: edges outside G_f
+    int induced;
+    const int32_t* par;      // parents: rows of (N-1 vertices, QP slot)
+    const uint64_t* padj;    // parent level: packed adjacency per QP slot
+    const uint8_t* svtab;
+    Rec R;
+    unsigned long long* ctr;   // [emitted, candidates, work counter, bytes]
+    int64_t nwork;
+    Sampling smp;            // ethr: this join's sampled neighbour lists
+    int64_t* counts;
+    const int64_t* offsets;
+    int32_t* out;
+    int64_t out_rows;
+};
+
+// Children of one (parent, position, new vertex u) candidate: the subsets
+// of u's connecting edges ec (ec itself when vertex-induced) whose child
+// the removal rule assigns to this (u, k).  PHASE 0 records (domain pass) or
+// counts; PHASE 1 writes the rows from dst.
+template <int N, int MODE, int PHASE>
+__device__ int single_children(const SingleArgs& a, const int32_t (&cv)[N], int i, uint32_t ec,
+                               uint64_t PA, uint32_t rpar, const int (&rkv)[N], uint8_t want,
+                               uint64_t kbase, uint64_t Lc, int32_t* dst) {
+    constexpr int M = N - 1;
+    int got = 0;
+    uint32_t sub = ec;
+    for (;;) {
+        uint32_t radj = rpar;
+        uint64_t A = add_edge(PA, i, M);
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if ((sub >> j) & 1u) {
+                radj |= rbit<N>(rkv[j], rkv[M]);
+                A = add_edge(A, j, M);
+            }
+        if (a.svtab[radj] == want) {
+            const uint64_t key = kbase | sub;
+            if (MODE == MODE_DOMAIN) {
+                record<N>(a.R, key, Lc, A, cv);
+                ++got;
+            } else {
+                const int64_t s = frequent_slot(a.R, key);
+                if (s >= 0) {
+                    if (PHASE == 1) {
+#pragma unroll
+                        for (int q = 0; q < N; ++q) dst[q] = cv[q];
+                        dst[N] = (int32_t)s;
+                        dst += N + 1;
+                    }
+                    ++got;
+                }
+            }
+        }
+        if (!sub || a.induced) break;
+        sub = (sub - 1) & ec;
+    }
+    return got;
+}
+
+// One wave per work item (parent p, position i), taken from a queue in
+// chunks; lanes over the neighbours u of k = p[i].  MODE_DOMAIN records the
+// children, MODE_COUNT / MODE_FILL count and write the frequent ones.
+template <int N, int MODE>
+__global__ __launch_bounds__(TPB) void k_single(SingleArgs a) {
+    constexpr int M = N - 1;
+    const int lane = threadIdx.x & 63;
+    unsigned long long emit = 0, cands = 0, bytes = 0;
+    for (;;) {
+        unsigned long long w0 = 0;
+        if (lane == 0) w0 = atomicAdd(&a.ctr[2], (unsigned long long)JOIN_CHUNK);
+        w0 = __shfl(w0, 0, 64);
+        if ((int64_t)w0 >= a.nwork) break;
+        const int64_t wend = min((int64_t)w0 + JOIN_CHUNK, a.nwork);
+        for (int64_t wi = (int64_t)w0; wi < wend; ++wi) {
+            const int64_t p = wi / M;
+            const int i = (int)(wi - p * M);
+            const int32_t* prow = a.par + p * (M + 1);
+            int32_t cv[N];
+#pragma unroll
+            for (int j = 0; j < M; ++j) cv[j] = prow[j];
+            const int32_t pslot = prow[M];
+            const uint64_t PA = a.padj[pslot];
+            int32_t k = cv[0];
+            uint64_t L = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j == i) k = cv[j];
+                L |= (uint64_t)a.vf[cv[j]] << (6 * j);
+            }
+            const int32_t rk = a.row[k], dk = a.row[k + 1] - rk;
+            if (lane == 0) {
+                cands += (unsigned long long)dk;
+                bytes += 4ull * (M + 1) + 4ull * (unsigned long long)dk;
+            }
+            int64_t base = (MODE == MODE_FILL) ? a.offsets[wi] : 0, total = 0;
+            for (int32_t r0 = 0; r0 < dk; r0 += 64) {
+                const int32_t r = r0 + lane;
+                int got = 0;
+                int32_t u = -1;
+                bool ok = r < dk;
+                if (ok) {
+                    u = a.col[rk + r];
+#pragma unroll
+                    for (int j = 0; j < M; ++j) ok = ok && cv[j] != u;
+                    // ST: the edge (k, u) must be one of k's sampled edges
+                    if (ok && a.smp.ethr && edge_hash(a.smp.seed, N, k, u) > a.smp.ethr[k])
+                        ok = false;
+                }
+                uint32_t ec = 0;
+                if (ok) {
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        if (j == i) continue;
+                        if (has_edge(a.nh, cv[j], u)) ec |= 1u << j;
+                        else if (a.induced && blocked(a.xh, cv[j], u)) ok = false;
+                    }
+                    bytes += 8ull * (M - 1);
+                }
+                int rkv[N];
+                uint32_t rpar = 0;
+                uint8_t want = 0;
+                uint64_t kbase = 0, Lc = 0;
+                if (ok) {
+                    cv[M] = u;
+                    const int lu = a.vf[u];
+                    Lc = L | (uint64_t)lu << (6 * M) | (uint64_t)a.vg[k] << 48;
+                    // ranks by id; the parent's edges and (k, u) in rank space
+#pragma unroll
+                    for (int q = 0; q < N; ++q) rkv[q] = 0;
+#pragma unroll
+                    for (int q = 0; q < N; ++q)
+#pragma unroll
+                        for (int s2 = q + 1; s2 < N; ++s2) {
+                            const int c = cv[q] < cv[s2] ? 1 : 0;
+                            rkv[s2] += c;
+                            rkv[q] += 1 - c;
+                        }
+                    int rki = 0;
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+                        if (q == i) rki = rkv[q];
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+#pragma unroll
+                        for (int s2 = q + 1; s2 < M; ++s2)
+                            if ((PA >> (8 * q + s2)) & 1u) rpar |= rbit<N>(rkv[q], rkv[s2]);
+                    rpar |= rbit<N>(rki, rkv[M]);
+                    want = (uint8_t)(rkv[M] | rki << 4);
+                    kbase = (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)lu << 24;
+                    got = single_children<N, MODE, 0>(a, cv, i, ec, PA, rpar, rkv, want, kbase,
+                                                      Lc, nullptr);
+                    bytes += 4ull * N * (unsigned long long)got;
+                }
+                if (MODE == MODE_DOMAIN) {
+                    emit += (unsigned long long)got;
+                } else {
+                    const int64_t ex = wave_excl((int64_t)got, lane);
+                    if (MODE == MODE_FILL && got) {
+                        const int64_t r2 = base + total + ex;
+                        if (r2 + got <= a.out_rows)
+                            single_children<N, MODE, 1>(a, cv, i, ec, PA, rpar, rkv, want, kbase,
+                                                        Lc, a.out + r2 * (N + 1));
+                        else
+                            atomicOr(a.R.flags, ERR_FILL);
+                    }
+                    total += wave_sum((int64_t)got);
+                }
+            }
+            if (MODE == MODE_COUNT && lane == 0) a.counts[wi] = total;
+        }
+    }
+    const int64_t te = wave_sum((int64_t)emit);
+    const int64_t tc = wave_sum((int64_t)cands);
+    const int64_t tb = wave_sum((int64_t)bytes);
+    if (lane == 0) {
+        if (te) atomicAdd(&a.ctr[0], (unsigned long long)te);
+        if (tc) atomicAdd(&a.ctr[1], (unsigned long long)tc);
+        if (tb) atomicAdd(&a.ctr[3], (unsigned long long)tb);
+    }
+}
+
 // ------------------------------------------------- fixed-size group samples
 //
 // Threshold of every group of a sampled loop (Section 5): one block per
@@ -1093,7 +1320,8 @@ __device__ uint64_t block_select(int64_t slots, uint64_t cap, const Units& units
 
 // KIND SEL_PIECES: group = joining vertex k, members = the stored size-3
 // subgraphs containing k (piece slots x their types) at the size-n join;
-// SEL_EDGES: members = k's G_f edges (size-4 join); SEL_MATCH: group =
+// SEL_EDGES: members = k's G_f edges (size-4 two-vertex join, every
+// single-vertex join); SEL_MATCH: group =
 // vertex c, members = the size-3 subgraphs credited to c in matching.
 template <int KIND>
 __global__ __launch_bounds__(SEL_TPB) void k_group_select(SelArgs a) {
@@ -1132,7 +1360,7 @@ __global__ __launch_bounds__(SEL_TPB) void k_group_select(SelArgs a) {
                 }, hist, sh);
             } else if (KIND == SEL_EDGES) {
                 res = block_select(slots, a.cap, [&](int64_t q, auto&& emit) {
-                    emit(edge_hash(a.smp.seed, kk, a.col[rk + q]));
+                    emit(edge_hash(a.smp.seed, a.n, kk, a.col[rk + q]));
                 }, hist, sh);
             } else {
                 res = block_select(slots, a.cap, [&](int64_t q, auto&& emit) {
@@ -1149,6 +1377,54 @@ __global__ __launch_bounds__(SEL_TPB) void k_group_select(SelArgs a) {
         if (threadIdx.x == 0) a.thr[k] = res;
         __syncthreads();
     }
+}
+
+// Hash-table accounting (Section 6.2's memory-access comparison): the size
+// of every joining vertex's key group, the stored size-3 subgraphs that
+// contain it (one wave per vertex, lanes over its piece slots), and the sum
+// of those sizes, capped at the ST sample, over a join's work items.
+__global__ __launch_bounds__(TPB) void k_key_group_sizes(SelArgs a, int64_t* size) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (TPB / 64);
+    for (int64_t k = wave_id_global(); k < a.groups; k += nw) {
+        const int32_t rk = a.row[k], dk = a.row[k + 1] - rk;
+        const int64_t ncen = (int64_t)dk * (dk - 1) / 2, Q = a.npieces[k];
+        const int lk = (int)(a.vinfo[k] >> 26);
+        const uint8_t* f3 = a.f3 + (size_t)a.vg[k] * 2 * a.F * a.F * a.F;
+        int64_t c = 0;
+        for (int64_t q = lane; q < Q; q += 64) {
+            int32_t u, w;
+            const bool centre = piece_at(a.row, a.col, a.leafoff, rk, dk, ncen, q, u, w);
+            if (w == (int32_t)k) continue;
+            unsigned long long by = 0;
+            const uint32_t types =
+                piece_types(f3, a.F, a.nh, a.xh, a.induced, centre, (int32_t)k, u, w, lk,
+                            (int)(a.vinfo[u] >> 26), (int)(a.vinfo[w] >> 26), by);
+            c += __popc(matched_types(a.smp, types, (int32_t)k, u, w));
+        }
+        c = wave_sum(c);
+        if (lane == 0) size[k] = c;
+    }
+}
+
+__global__ void k_degrees(const int32_t* row, int64_t n, int64_t* deg) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        deg[v] = row[v + 1] - row[v];
+}
+
+__global__ void k_item_group_sum(const int32_t* par, int64_t rows, int M, const int64_t* size,
+                                 int64_t cap, unsigned long long* out) {
+    unsigned long long t = 0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x)
+        for (int j = 0; j < M; ++j) {
+            const int64_t g = size[par[r * (M + 1) + j]];
+            t += (unsigned long long)(cap > 0 && g > cap ? cap : g);
+        }
+    const int lane = threadIdx.x & 63;
+    const int64_t s = wave_sum((int64_t)t);
+    if (lane == 0 && s) atomicAdd(out, (unsigned long long)s);
 }
 
 // ------------------------------------------------------------ join, tiled
@@ -1304,14 +1580,6 @@ struct LaneCache {
     uint64_t k0, v0, k1, v1;   // QP lookups (persist across tiles)
     uint64_t b0, b1;           // bits done in this tile
 };
-
-// Rank-space pair bit: vertices ordered by id, pair (a, b) of ranks in the
-// row-major upper-triangle order of an N-vertex graph.
-template <int N>
-__device__ __forceinline__ uint32_t rbit(int a, int b) {
-    const int lo = a < b ? a : b, hi = a < b ? b : a;
-    return 1u << (lo * N - lo * (lo + 1) / 2 + (hi - lo - 1));
-}
 
 // Adjacency of every parent vertex except k with the piece's two new
 // vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  The parent vertex
@@ -1573,6 +1841,9 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const int32_t pb = (int32_t)(a.goff[g] + pt * a.tile_p);
         const int32_t pe = (int32_t)min(a.goff[g] + a.gcnt[g], (int64_t)pb + a.tile_p);
         if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
+        // no lane holds a piece the join may take (infrequent or unsampled):
+        // the tile has no children
+        if (__ballot(types != 0) == 0ull) continue;
         c.b0 = c.b1 = 0;
         for (int32_t pp = pb; pp < pe; ++pp) {
             const int32_t* prow = a.par + (int64_t)a.glist[pp] * (M + 1);
@@ -1606,7 +1877,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             for (int j = 0; j < M; ++j) ok = ok && cv[j] != u && cv[j] != w;
             // ST at the size-4 join: the parent edge must be one of the
             // sampled edges of k's key group (wave-uniform)
-            if (EXTRA && N == 4 && a.smp.ethr && edge_hash(a.smp.seed, k, cv[1 - i]) > a.smp.ethr[k])
+            if (EXTRA && N == 4 && a.smp.ethr && edge_hash(a.smp.seed, 4, k, cv[1 - i]) > a.smp.ethr[k])
                 ok = false;
             // n = 4: the smallest vertex of every child lies in the accepted
             // size-3 part (exhaustively true for connected graphs on 4
@@ -2435,6 +2706,7 @@ struct Miner {
     void build_gf();
     void level3();
     void join(int n);
+    void join_single(int n);
     void emit_results();
 };
 
@@ -2513,7 +2785,7 @@ void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32
 // Thresholds of every vertex's group of a fixed-size sample (Section 5):
 // kind SEL_MATCH (size-3 subgraphs credited to the vertex), SEL_PIECES
 // (stored size-3 subgraphs containing the joining vertex, size-n join) or
-// SEL_EDGES (its G_f edges, size-4 join); cap members per group.
+// SEL_EDGES (its G_f edges at a size-n edge join); cap members per group.
 void Miner::group_thresholds(int kind, int n, uint64_t cap, DBuf<uint64_t>& thr) {
     thr.alloc((size_t)g->n);
     SelArgs a;
@@ -2829,6 +3101,27 @@ void Miner::join(int n) {
     const uint64_t thr =
         opt.sampling_rate >= 1.0 ? ~0ull
                                  : (uint64_t)std::ldexp(opt.sampling_rate, 64);
+    // hash-table bytes: 12 per stored size-3 subgraph of each work item's
+    // key group (capped at the ST sample)
+    if (nwork > 0) {
+        DBuf<int64_t> gsize((size_t)g->n);
+        SelArgs sa;
+        sa.row = frow.p; sa.col = fcol.p; sa.leafoff = leafoff.p; sa.npieces = npieces.p;
+        sa.vinfo = vinfo.p; sa.vg = g->vg; sa.f3 = f3.p; sa.F = F;
+        sa.nh = nh(); sa.xh = xh();
+        sa.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+        sa.smp = sampling();
+        sa.n = n; sa.groups = g->n; sa.cap = 0; sa.thr = nullptr;
+        k_key_group_sizes<<<grid_for(g->n, TPB / 64), TPB, 0, st>>>(sa, gsize.p);
+        FSM_LAUNCH_CHECK();
+        DBuf<unsigned long long> hb(1);
+        hb.zero();
+        const int64_t cap = opt.join_threshold > 0 ? opt.join_threshold * opt.join_threshold : 0;
+        k_item_group_sum<<<grid_for(P.rows, TPB, 4096), TPB, 0, st>>>(P.emb.p, P.rows, M, gsize.p,
+                                                                     cap, hb.p);
+        FSM_LAUNCH_CHECK();
+        L.st.hash_bytes = 12 * (int64_t)scalar_to_host(hb.p);
+    }
     // ST x (Section 5): x^2 size-3 subgraphs per key group at every join,
     // and x edges per key group at the size-4 join
     Sampling smp = sampling();
@@ -2995,6 +3288,102 @@ void Miner::join(int n) {
     }
 }
 
+// Single-vertex join of size n: parents of size n-1 joined with one edge
+// at each of their vertices (the baseline of Section 6).
+void Miner::join_single(int n) {
+    Level& L = lv[n];
+    Level& P = lv[n - 1];
+    L.n = n;
+    const int M = n - 1;
+    const int64_t nwork = P.rows * M;
+    L.st.parents = P.rows;
+    L.st.work_items = nwork;
+    Sampling smp = sampling();
+    DBuf<uint64_t> ethr;
+    if (opt.join_threshold > 0 && nwork > 0) {
+        group_thresholds(SEL_EDGES, n, (uint64_t)opt.join_threshold, ethr);
+        smp.ethr = ethr.p;
+    }
+    // hash-table bytes: 8 per G_f edge of each work item's joining vertex
+    // (capped at the ST sample)
+    if (nwork > 0) {
+        DBuf<int64_t> deg((size_t)g->n);
+        k_degrees<<<grid_for(g->n, TPB), TPB, 0, st>>>(frow.p, g->n, deg.p);
+        FSM_LAUNCH_CHECK();
+        DBuf<unsigned long long> hb(1);
+        hb.zero();
+        k_item_group_sum<<<grid_for(P.rows, TPB, 4096), TPB, 0, st>>>(
+            P.emb.p, P.rows, M, deg.p, opt.join_threshold, hb.p);
+        FSM_LAUNCH_CHECK();
+        L.st.hash_bytes = 8 * (int64_t)scalar_to_host(hb.p);
+    }
+    const uint32_t tsize = 1u << (n * (n - 1) / 2);
+    DBuf<uint8_t> svtab(tsize);
+    k_single_table<<<grid_for(tsize, TPB), TPB, 0, st>>>(n, svtab.p);
+    FSM_LAUNCH_CHECK();
+    auto args = [&](Rec R, int64_t* counts, const int64_t* offsets, int32_t* out, int64_t rows) {
+        SingleArgs a;
+        a.row = frow.p; a.col = fcol.p; a.vf = vf.p; a.vg = g->vg;
+        a.nh = nh(); a.xh = xh();
+        a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+        a.par = P.emb.p; a.padj = P.tab.qadj.p;
+        a.svtab = svtab.p;
+        a.R = R;
+        a.ctr = counters.p;
+        a.nwork = nwork;
+        a.smp = smp;
+        a.counts = counts; a.offsets = offsets; a.out = out; a.out_rows = rows;
+        return a;
+    };
+    auto launch = [&](int mode, const SingleArgs& a) {
+#define FSM_SINGLE_CASE(NN)                                                                  \
+    case NN:                                                                                 \
+        if (mode == MODE_DOMAIN) k_single<NN, MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a); \
+        else if (mode == MODE_COUNT) k_single<NN, MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a); \
+        else k_single<NN, MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);                     \
+        break;
+        switch (n) {
+            FSM_SINGLE_CASE(3)
+            FSM_SINGLE_CASE(4)
+            FSM_SINGLE_CASE(5)
+            FSM_SINGLE_CASE(6)
+            FSM_SINGLE_CASE(7)
+            default: fail(FSM_EINVAL, "bad join size %d", n);
+        }
+#undef FSM_SINGLE_CASE
+        FSM_LAUNCH_CHECK();
+    };
+    hipEvent_t j0, j1;
+    FSM_HIP(hipEventCreate(&j0));
+    FSM_HIP(hipEventCreate(&j1));
+    try {
+        float join_total = 0.f;
+        domain_level(L, [&](Rec R, int pass) {
+            if (pass == 0) join_total = 0.f;
+            FSM_HIP(hipEventRecord(j0, st));
+            if (nwork > 0) launch(MODE_DOMAIN, args(R, nullptr, nullptr, nullptr, 0));
+            FSM_HIP(hipEventRecord(j1, st));
+            float ms = 0;
+            FSM_HIP(hipEventSynchronize(j1));
+            FSM_HIP(hipEventElapsedTime(&ms, j0, j1));
+            join_total += ms;
+        });
+        L.st.join_ms = join_total;
+    } catch (...) {
+        (void)hipEventDestroy(j0);
+        (void)hipEventDestroy(j1);
+        throw;
+    }
+    (void)hipEventDestroy(j0);
+    (void)hipEventDestroy(j1);
+    if (n + 1 <= opt.max_size) {
+        materialize(L, nwork, [&](int mode, int64_t* counts, const int64_t* offsets, int32_t* out,
+                                  int64_t rows) {
+            if (nwork > 0) launch(mode, args(rec(L), counts, offsets, out, rows));
+        });
+    }
+}
+
 void Miner::emit_results() {
     if (opt.record) {
         const size_t rows = rl.size();
@@ -3108,45 +3497,59 @@ void Miner::run() {
         FSM_HIP(hipEventElapsedTime(&ms, e0, e1));
         lv[n].st.kernel_ms = ms;
     };
+    // level-2 embeddings: the edges of G_f (u < w)
+    auto materialize_edges = [&] {
+        Level& L = lv[2];
+        materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets, int32_t* out,
+                                 int64_t rows) {
+            L2Args a{frow.p, fcol.p, vf.p, g->vg, g->n, rec(L), counters.p, counts, offsets, out,
+                     rows};
+            if (mode == MODE_COUNT) k_level2<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
+            else k_level2<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
+            FSM_LAUNCH_CHECK();
+        });
+    };
     try {
         timed(2, [&] { level2(); });
         build_gf();
-        if (opt.max_size >= 3) timed(3, [&] { level3(); });
-        // level-2 embeddings (edges of G_f, u < w) for the size-4 join
-        if (opt.max_size >= 4) {
-            Level& L = lv[2];
-            materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
-                                     int32_t* out, int64_t rows) {
-                L2Args a{frow.p, fcol.p, vf.p, g->vg, g->n, rec(L), counters.p, counts, offsets,
-                         out, rows};
-                if (mode == MODE_COUNT) k_level2<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
-                else k_level2<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
-                FSM_LAUNCH_CHECK();
-            });
-        }
-        if (opt.max_size >= 5) {
-            Level& L = lv[3];
-            materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
-                                     int32_t* out, int64_t rows) {
-                L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), rec(L), counters.p,
-                         counts, offsets, out, rows};
-                a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
-                a.xh = xh();
-                a.smp = sampling();
-                if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
-                else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
-                FSM_LAUNCH_CHECK();
-            });
-        }
-        if (opt.max_size < 4) lv[2].tab = Tables();
-        if (opt.max_size < 5) lv[3].tab = Tables();
-        for (int n = 4; n <= opt.max_size; ++n) {
-            timed(n, [&] { join(n); });
-            // size n-2 embeddings and their QP table are no longer needed,
-            // nor the size-n table when no later join reads it
-            lv[n - 2].emb.reset();
-            lv[n - 2].tab = Tables();
-            if (n + 2 > opt.max_size) lv[n].tab = Tables();
+        if (opt.mode & FSM_SINGLE) {
+            // single-vertex exploration: one-edge joins from the edges up
+            if (opt.max_size >= 3) materialize_edges();
+            else lv[2].tab = Tables();
+            for (int n = 3; n <= opt.max_size; ++n) {
+                timed(n, [&] { join_single(n); });
+                lv[n - 1].emb.reset();
+                lv[n - 1].tab = Tables();
+                if (n + 1 > opt.max_size) lv[n].tab = Tables();
+            }
+        } else {
+            if (opt.max_size >= 3) timed(3, [&] { level3(); });
+            // the edges are the parents of the size-4 join
+            if (opt.max_size >= 4) materialize_edges();
+            if (opt.max_size >= 5) {
+                Level& L = lv[3];
+                materialize(L, g->n, [&](int mode, int64_t* counts, const int64_t* offsets,
+                                         int32_t* out, int64_t rows) {
+                    L3Args a{frow.p, fcol.p, vf.p, g->vg, g->n, nh(), rec(L), counters.p,
+                             counts, offsets, out, rows};
+                    a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+                    a.xh = xh();
+                    a.smp = sampling();
+                    if (mode == MODE_COUNT) k_level3<MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a);
+                    else k_level3<MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);
+                    FSM_LAUNCH_CHECK();
+                });
+            }
+            if (opt.max_size < 4) lv[2].tab = Tables();
+            if (opt.max_size < 5) lv[3].tab = Tables();
+            for (int n = 4; n <= opt.max_size; ++n) {
+                timed(n, [&] { join(n); });
+                // size n-2 embeddings and their QP table are no longer needed,
+                // nor the size-n table when no later join reads it
+                lv[n - 2].emb.reset();
+                lv[n - 2].tab = Tables();
+                if (n + 2 > opt.max_size) lv[n].tab = Tables();
+            }
         }
     } catch (...) {
         (void)hipEventDestroy(e0);
