@@ -11,6 +11,9 @@ longest domain pass), timed with HIP events on its launch stream.
 ``cpu_baseline`` is the single-thread CPU oracle on the same workload.
 ``batch`` compares plain per-graph calls with batched+learned mining on the
 256-graph workload (same device, identical results required).
+``single_vertex`` mines the same graph by single-vertex exploration (the
+paper's baseline) and ``sampling`` with sampling thresholds ST 2..16,
+scored against the exact result.
 """
 import argparse
 import json
@@ -167,6 +170,47 @@ def cost_model_leg(fsm, synth, max_size=5):
     return out
 
 
+def single_vertex_leg(fsm, g, t, smax, ref):
+    """Single-vertex exploration (the baseline of Section 6) on the same
+    graph: identical results required; wall time, join time, hash-table
+    lookups (one per work item) and the bytes of the key groups read."""
+    sv = fsm.mine(g, t, smax, fsm.FSM_SINGLE)
+    assert sv.patterns == ref.patterns, "single-vertex results differ"
+    lt, ls = ref.stats["levels"], sv.stats["levels"]
+    tv_n, sv_n = range(4, smax + 1), range(3, smax + 1)
+    out = {
+        "two_vertex_ms": round(ref.stats["total_ms"], 1),
+        "single_vertex_ms": round(sv.stats["total_ms"], 1),
+        "two_vertex_join_ms": round(sum(lt[n]["join_ms"] for n in tv_n), 1),
+        "single_vertex_join_ms": round(sum(ls[n]["join_ms"] for n in sv_n), 1),
+        "two_vertex_lookups": sum(lt[n]["work_items"] for n in tv_n),
+        "single_vertex_lookups": sum(ls[n]["work_items"] for n in sv_n),
+        "two_vertex_hash_bytes": sum(lt[n]["hash_bytes"] for n in tv_n),
+        "single_vertex_hash_bytes": sum(ls[n]["hash_bytes"] for n in sv_n),
+    }
+    out["slowdown"] = round(out["single_vertex_ms"] / out["two_vertex_ms"], 3)
+    out["lookup_ratio"] = round(out["single_vertex_lookups"] / max(1, out["two_vertex_lookups"]), 2)
+    print(f"[bench] single-vertex: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def sampling_leg(fsm, g, t, smax, ref):
+    """Fixed-size subgraph sampling (Section 5, ST x) scored against the
+    exact result: patterns found (all are exactly frequent; supports are
+    lower bounds) and wall time, two- and single-vertex."""
+    exact = {(p[0], p[1], p[2]): p[3] for p in ref.patterns}
+    rows = []
+    for x in (2, 4, 8, 16):
+        for name, mode in (("two_vertex", 0), ("single_vertex", fsm.FSM_SINGLE)):
+            r = fsm.mine(g, t, smax, mode, join_threshold=x, seed=5)
+            got = {(p[0], p[1], p[2]): p[3] for p in r.patterns}
+            assert all(k in exact and v <= exact[k] for k, v in got.items())
+            rows.append({"st": x, "mode": name, "found": len(got), "exact": len(exact),
+                         "ms": round(r.stats["total_ms"], 1)})
+    print(f"[bench] sampling: {rows}", file=sys.stderr, flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +223,10 @@ def main():
     ap.add_argument("--cost-model-leg", action="store_true",
                     help="also mine the 1M-vertex, 37-label workload (sizes 2..5) with plain "
                          "and with learned table sizing")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-vertex exploration comparison")
+    ap.add_argument("--no-sampling", action="store_true",
+                    help="skip the ST-sampled runs scored against the exact result")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one elementwise int32 kernel that reads and "
                          "writes this many MiB (calibrates profiler byte counters)")
@@ -242,10 +290,12 @@ def main():
                         "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4)}
         roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                    "traffic": traffic, "kernel": f"k_join_tiles<{dom}> (domain pass)",
+                    "traffic": traffic, "kernel": f"k_join_tiles<{dom}, false> (domain pass)",
                     "kernel_ms": round(ms, 3), "algorithmic_bytes": nbytes,
                     "valu": valu}
 
+    single = None if args.no_single else single_vertex_leg(fsm, g, t, smax, ref)
+    sampled = None if args.no_sampling else sampling_leg(fsm, g, t, smax, ref)
     batch = None if args.no_batch else batch_comparison(fsm, synth)
     learned = cost_model_leg(fsm, synth) if args.cost_model_leg else None
 
@@ -284,6 +334,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batch": batch,
+        "single_vertex": single,
+        "sampling": sampled,
     }
     if learned is not None:
         out["cost_model"] = learned
