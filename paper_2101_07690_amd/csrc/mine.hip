@@ -1114,7 +1114,8 @@ __device__ int single_children(const SingleArgs& a, const int32_t (&cv)[N], int 
 
 // One wave per work item (parent p, position i), taken from a queue in
 // chunks; lanes over the neighbours u of k = p[i].  MODE_DOMAIN records the
-// children, MODE_COUNT / MODE_FILL count and write the frequent ones.
+// children (the tiled kernel below does this for the library),
+// MODE_COUNT / MODE_FILL count and write the frequent ones.
 template <int N, int MODE>
 __global__ __launch_bounds__(TPB) void k_single(SingleArgs a) {
     constexpr int M = N - 1;
@@ -1838,14 +1839,15 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         if (N == 5 && !a.pkey) sort3(k, u, w, q0, q1, q2);
         // sorted lists: the tile's smallest key (every lane's key is >= it)
         const uint64_t tkey = (N == 5 && a.pkey) ? a.pkey[a.poff[k] + qt * 64] : 0;
-        const int32_t pb = (int32_t)(a.goff[g] + pt * a.tile_p);
-        const int32_t pe = (int32_t)min(a.goff[g] + a.gcnt[g], (int64_t)pb + a.tile_p);
+        // parent range of the tile in glist (work items can exceed 2^31)
+        const int64_t pb = a.goff[g] + pt * a.tile_p;
+        const int64_t pe = min(a.goff[g] + a.gcnt[g], pb + a.tile_p);
         if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
         // no lane holds a piece the join may take (infrequent or unsampled):
         // the tile has no children
         if (__ballot(types != 0) == 0ull) continue;
         c.b0 = c.b1 = 0;
-        for (int32_t pp = pb; pp < pe; ++pp) {
+        for (int64_t pp = pb; pp < pe; ++pp) {
             const int32_t* prow = a.par + (int64_t)a.glist[pp] * (M + 1);
             int32_t cv[N], lr[N];
             int i = 0;
@@ -1929,6 +1931,217 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     if (a.item_children && lane == 0 && run_sum)
         atomicAdd(&a.item_children[run_item], (unsigned long long)run_sum);
+    const int64_t te = wave_sum((int64_t)emit);
+    const int64_t tc = wave_sum((int64_t)cands);
+    const int64_t tb = wave_sum((int64_t)bytes);
+    if (lane == 0) {
+        if (te) atomicAdd(&a.ctr[0], (unsigned long long)te);
+        if (tc) atomicAdd(&a.ctr[1], (unsigned long long)tc);
+        if (tb) atomicAdd(&a.ctr[3], (unsigned long long)tb);
+    }
+}
+
+// Domain pass of the single-vertex join, tiled like the two-vertex one:
+// work items grouped by (k = p[i], parent QP, i); a tile = up to tile_p
+// parents of a group x 64 neighbours u of k (one per lane; a list of D <= 32
+// neighbours serves 64 / D parents at a time).  Within a group a lane's
+// child QP depends only on u's connecting edges, so the two-entry QP cache
+// hits, and the bits of k and u are set once per (lane, QP) per tile.
+struct SingleTileArgs {
+    const int32_t* row;      // G_f
+    const int32_t* col;
+    const uint32_t* vinfo;   // frequent label << 26 | rank within the label
+    const int32_t* vg;
+    NbrHash nh;
+    NbrHash xh;
+    int induced;
+    const int32_t* par;
+    const uint64_t* padj;
+    const int32_t* gk;
+    const int64_t* goff;
+    const int64_t* gcnt;
+    const int64_t* toff;
+    int64_t ngroups;
+    int64_t ntiles;
+    const int32_t* glist;
+    int tile_p;
+    const uint8_t* svtab;
+    uint32_t* bits;
+    uint32_t W;
+    int32_t rbase;
+    const Rec* rec;
+    const uint32_t* flags;
+    unsigned long long* ctr;   // [emitted, candidates, tile counter, bytes]
+    Sampling smp;              // ethr: this join's sampled neighbour lists
+};
+
+template <int N>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_single_tiles(
+    SingleTileArgs a) {
+    constexpr int M = N - 1;
+    const int lane = threadIdx.x & 63;
+    unsigned long long emit = 0, cands = 0, bytes = 0;
+    LaneCache c{EMPTY_KEY, 0, EMPTY_KEY, 0, 0, 0};
+    int64_t g = 0;
+    for (;;) {
+        unsigned long long nt = 0;
+        if (lane == 0) nt = atomicAdd(&a.ctr[2], 1ull);
+        const int64_t t = (int64_t)__shfl(nt, 0, 64);
+        if (t >= a.ntiles) break;
+        if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & OVF_QP)
+            break;
+        {   // group of tile t (t only grows: gallop)
+            int64_t step = 1;
+            while (g + step < a.ngroups && a.toff[g + step] <= t) { g += step; step <<= 1; }
+            int64_t lo = g, hi = min(g + step, a.ngroups - 1);
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) >> 1;
+                if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            g = lo;
+        }
+        const int32_t k = a.gk[g];
+        const int32_t rk = a.row[k];
+        const int64_t Q = a.row[k + 1] - rk;
+        const int64_t nqt = (Q + 63) / 64;
+        const int64_t local = t - a.toff[g];
+        const int64_t pt = local / nqt, qt = local - pt * nqt;
+        // short neighbour lists (<= 32) pack 64 / D parents per step into
+        // the wave, D = the list length rounded up to a power of two
+        int D = 64;
+        if (Q <= 32) {
+            D = 1;
+            while (D < Q) D <<= 1;
+        }
+        const int64_t q = qt * 64 + (lane & (D - 1));
+        const int sub0 = lane / D, step = 64 / D;
+        int32_t u = -1, lru = 0;
+        int lu = 0;
+        bool live = q < Q;
+        if (live) {
+            u = a.col[rk + q];
+            bytes += 4;
+            // ST: the edge (k, u) must be one of k's sampled edges
+            if (a.smp.ethr && edge_hash(a.smp.seed, N, k, u) > a.smp.ethr[k]) live = false;
+            const uint32_t iu = a.vinfo[u];
+            lu = (int)(iu >> 26);
+            lru = (int32_t)(iu & RANK_MASK);
+        }
+        // parent range of the tile in glist (work items can exceed 2^31)
+        const int64_t pb = a.goff[g] + pt * a.tile_p;
+        const int64_t pe = min(a.goff[g] + a.gcnt[g], pb + a.tile_p);
+        if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
+        if (__ballot(live) == 0ull) continue;
+        c.b0 = c.b1 = 0;
+        const uint64_t gid = (uint64_t)a.vg[k];
+        for (int64_t pp = pb + sub0; pp < pe; pp += step) {
+            const int32_t* prow = a.par + (int64_t)a.glist[pp] * (M + 1);
+            int32_t cv[N], lr[N];
+            int i = 0;
+            uint64_t L = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                cv[j] = prow[j];
+                if (cv[j] == k) i = j;
+            }
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const uint32_t vi = a.vinfo[cv[j]];
+                lr[j] = (int32_t)(vi & RANK_MASK);
+                L |= (uint64_t)(vi >> 26) << (6 * j);
+            }
+            if ((lane & (D - 1)) == 0) bytes += 4ull * (M + 1);
+            const int32_t pslot = prow[M];
+            bool ok = live;
+#pragma unroll
+            for (int j = 0; j < M; ++j) ok = ok && cv[j] != u;
+            int got = 0;
+            if (ok) {
+                const uint64_t PA = a.padj[pslot];
+                uint32_t ec = 0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    if (j == i) continue;
+                    if (has_edge(a.nh, cv[j], u)) ec |= 1u << j;
+                    else if (a.induced && blocked(a.xh, cv[j], u)) ok = false;
+                }
+                bytes += 8ull * (M - 1);
+                cv[M] = u;
+                lr[M] = lru;
+                int rkv[N];
+#pragma unroll
+                for (int x = 0; x < N; ++x) rkv[x] = 0;
+#pragma unroll
+                for (int x = 0; x < N; ++x)
+#pragma unroll
+                    for (int y = x + 1; y < N; ++y) {
+                        const int cc = cv[x] < cv[y] ? 1 : 0;
+                        rkv[y] += cc;
+                        rkv[x] += 1 - cc;
+                    }
+                int rki = 0;
+#pragma unroll
+                for (int x = 0; x < M; ++x)
+                    if (x == i) rki = rkv[x];
+                uint32_t rpar = rbit<N>(rki, rkv[M]);
+#pragma unroll
+                for (int x = 0; x < M; ++x)
+#pragma unroll
+                    for (int y = x + 1; y < M; ++y)
+                        if ((PA >> (8 * x + y)) & 1u) rpar |= rbit<N>(rkv[x], rkv[y]);
+                const uint8_t want = (uint8_t)(rkv[M] | rki << 4);
+                const uint64_t kbase =
+                    (uint64_t)pslot << 35 | (uint64_t)i << 32 | (uint64_t)lu << 24;
+                const uint64_t Lc = L | (uint64_t)lu << (6 * M) | gid << 48;
+                uint32_t sub = ec;
+                while (ok) {
+                    uint32_t radj = rpar;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        if ((sub >> j) & 1u) radj |= rbit<N>(rkv[j], rkv[M]);
+                    if (a.svtab[radj] == want) {
+                        const uint64_t key = kbase | sub;
+                        int64_t sl;
+                        if (key == c.k0) {
+                            sl = (int64_t)c.v0;
+                        } else if (key == c.k1) {
+                            sl = (int64_t)c.v1;
+                        } else {
+                            uint64_t A = add_edge(PA, i, M);
+#pragma unroll
+                            for (int j = 0; j < M; ++j)
+                                if ((sub >> j) & 1u) A = add_edge(A, j, M);
+                            sl = qp_slot(*a.rec, key, Lc, A);
+                            if (sl >= 0) {
+                                c.k1 = c.k0; c.v1 = c.v0;
+                                c.k0 = key; c.v0 = (uint64_t)sl;
+                            }
+                        }
+                        if (sl >= 0) {
+                            uint32_t* base = a.bits + (uint64_t)sl * N * a.W;
+                            // k and u: once per QP per tile
+                            if ((uint64_t)sl + 1 != c.b0 && (uint64_t)sl + 1 != c.b1) {
+                                set_bit_in(base + (uint64_t)i * a.W, lr[i], a.rbase, a.W);
+                                set_bit_in(base + (uint64_t)M * a.W, lr[M], a.rbase, a.W);
+                                c.b1 = c.b0;
+                                c.b0 = (uint64_t)sl + 1;
+                            }
+#pragma unroll
+                            for (int j = 0; j < M; ++j) {
+                                if (j == i) continue;
+                                set_bit_in(base + (uint64_t)j * a.W, lr[j], a.rbase, a.W);
+                            }
+                        }
+                        ++got;
+                    }
+                    if (!sub || a.induced) break;
+                    sub = (sub - 1) & ec;
+                }
+                emit += (unsigned long long)got;
+                bytes += 4ull * N * (unsigned long long)got;
+            }
+        }
+    }
     const int64_t te = wave_sum((int64_t)emit);
     const int64_t tc = wave_sum((int64_t)cands);
     const int64_t tb = wave_sum((int64_t)bytes);
@@ -2695,7 +2908,8 @@ struct Miner {
         int64_t ngroups = 0, ntiles = 0;
         int tile_p = TILE_P_MAX;
     };
-    void build_groups(const Level& P, int M, int64_t nwork, Groups& G);
+    void build_groups(const Level& P, int M, int64_t nwork, Groups& G,
+                      const int64_t* pieces = nullptr);
     void sorted_pieces(DBuf<int64_t>& poff, DBuf<uint64_t>& key, DBuf<uint8_t>& code);
     void order_groups(const Level& P, int M, const ItemRows& IR, const float* y, Groups& G);
     void proposal_thresholds(const ItemRows& IR, const float* y, int64_t nitems,
@@ -2845,7 +3059,9 @@ void Miner::level3() {
 
 // Group the work items (p, i) of a join by (p[i], parent QP, i) and count
 // the (parents x pieces) tiles of every group.
-void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G) {
+// pieces: candidates per joining vertex (null: its size-3 piece slots)
+void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
+                         const int64_t* pieces) {
     if (nwork > (int64_t)INT32_MAX * M)
         fail(FSM_EUNSUPPORTED, "more than 2^31-1 parent embeddings");
     const int64_t n = g->n;
@@ -2903,8 +3119,8 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G) {
     const int tpw = opt.tiles_per_wave > 0 ? opt.tiles_per_wave : (tuned > 0 ? tuned : 16);
     const int64_t want = (int64_t)tpw * grid_persistent * (TPB / 64);
     for (G.tile_p = TILE_P_MAX;; G.tile_p /= 2) {
-        k_key_tiles<<<grid_for(G.ngroups, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p,
-                                                              G.ngroups, G.tile_p, tiles.p);
+        k_key_tiles<<<grid_for(G.ngroups, TPB), TPB, 0, st>>>(
+            G.gk.p, G.gcnt.p, pieces ? pieces : npieces.p, G.ngroups, G.tile_p, tiles.p);
         FSM_LAUNCH_CHECK();
         G.ntiles = scan_exclusive(tiles.p, G.toff.p, G.ngroups);
         if (G.tile_p == 1 || G.ntiles >= want) break;
@@ -3306,10 +3522,10 @@ void Miner::join_single(int n) {
     }
     // hash-table bytes: 8 per G_f edge of each work item's joining vertex
     // (capped at the ST sample)
+    DBuf<int64_t> deg((size_t)g->n);
+    k_degrees<<<grid_for(g->n, TPB), TPB, 0, st>>>(frow.p, g->n, deg.p);
+    FSM_LAUNCH_CHECK();
     if (nwork > 0) {
-        DBuf<int64_t> deg((size_t)g->n);
-        k_degrees<<<grid_for(g->n, TPB), TPB, 0, st>>>(frow.p, g->n, deg.p);
-        FSM_LAUNCH_CHECK();
         DBuf<unsigned long long> hb(1);
         hb.zero();
         k_item_group_sum<<<grid_for(P.rows, TPB, 4096), TPB, 0, st>>>(
@@ -3338,8 +3554,7 @@ void Miner::join_single(int n) {
     auto launch = [&](int mode, const SingleArgs& a) {
 #define FSM_SINGLE_CASE(NN)                                                                  \
     case NN:                                                                                 \
-        if (mode == MODE_DOMAIN) k_single<NN, MODE_DOMAIN><<<grid_persistent, TPB, 0, st>>>(a); \
-        else if (mode == MODE_COUNT) k_single<NN, MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a); \
+        if (mode == MODE_COUNT) k_single<NN, MODE_COUNT><<<grid_persistent, TPB, 0, st>>>(a); \
         else k_single<NN, MODE_FILL><<<grid_persistent, TPB, 0, st>>>(a);                     \
         break;
         switch (n) {
@@ -3353,6 +3568,25 @@ void Miner::join_single(int n) {
 #undef FSM_SINGLE_CASE
         FSM_LAUNCH_CHECK();
     };
+    Groups G;
+    if (nwork > 0) build_groups(P, M, nwork, G, deg.p);
+    auto tile_args = [&](Rec R) {
+        hrec = R;
+        FSM_HIP(hipMemcpyAsync(drec.p, &hrec, sizeof(Rec), hipMemcpyHostToDevice, st));
+        SingleTileArgs t;
+        t.row = frow.p; t.col = fcol.p; t.vinfo = vinfo.p; t.vg = g->vg;
+        t.nh = nh(); t.xh = xh();
+        t.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
+        t.par = P.emb.p; t.padj = P.tab.qadj.p;
+        t.gk = G.gk.p; t.goff = G.goff.p; t.gcnt = G.gcnt.p; t.toff = G.toff.p;
+        t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p; t.tile_p = G.tile_p;
+        t.svtab = svtab.p;
+        t.bits = R.pool.words; t.W = R.pool.W; t.rbase = R.pool.rbase; t.rec = drec.p;
+        t.flags = R.flags;
+        t.ctr = counters.p;
+        t.smp = smp;
+        return t;
+    };
     hipEvent_t j0, j1;
     FSM_HIP(hipEventCreate(&j0));
     FSM_HIP(hipEventCreate(&j1));
@@ -3361,7 +3595,18 @@ void Miner::join_single(int n) {
         domain_level(L, [&](Rec R, int pass) {
             if (pass == 0) join_total = 0.f;
             FSM_HIP(hipEventRecord(j0, st));
-            if (nwork > 0) launch(MODE_DOMAIN, args(R, nullptr, nullptr, nullptr, 0));
+            if (G.ntiles > 0) {
+                const SingleTileArgs t = tile_args(R);
+                switch (n) {
+                    case 3: k_single_tiles<3><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 4: k_single_tiles<4><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 5: k_single_tiles<5><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 6: k_single_tiles<6><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    case 7: k_single_tiles<7><<<grid_persistent, TPB, 0, st>>>(t); break;
+                    default: fail(FSM_EINVAL, "bad join size %d", n);
+                }
+                FSM_LAUNCH_CHECK();
+            }
             FSM_HIP(hipEventRecord(j1, st));
             float ms = 0;
             FSM_HIP(hipEventSynchronize(j1));
