@@ -1380,6 +1380,47 @@ __global__ __launch_bounds__(SEL_TPB) void k_group_select(SelArgs a) {
     }
 }
 
+// ST: the pieces that every joining vertex's key group keeps at the size-n
+// join (a.smp.kthr), as (min, max) key / code lists in piece order, the
+// format of the sorted size-5 lists -- the join then enumerates only them.
+// off == null: count into cnt; else write at off[k].  One wave per vertex.
+__global__ __launch_bounds__(TPB) void k_st_pieces(SelArgs a, const int64_t* off, int64_t* cnt,
+                                                   uint64_t* key, uint8_t* code) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (TPB / 64);
+    for (int64_t k = wave_id_global(); k < a.groups; k += nw) {
+        const int32_t rk = a.row[k], dk = a.row[k + 1] - rk;
+        const int64_t ncen = (int64_t)dk * (dk - 1) / 2, Q = a.npieces[k];
+        const int lk = (int)(a.vinfo[k] >> 26);
+        const uint8_t* f3 = a.f3 + (size_t)a.vg[k] * 2 * a.F * a.F * a.F;
+        int64_t done = 0;
+        for (int64_t q0 = 0; q0 < Q; q0 += 64) {
+            const int64_t q = q0 + lane;
+            int32_t u = -1, w = -1;
+            bool centre = false, keep = false;
+            if (q < Q) {
+                centre = piece_at(a.row, a.col, a.leafoff, rk, dk, ncen, q, u, w);
+                if (w != (int32_t)k) {
+                    unsigned long long by = 0;
+                    uint32_t types =
+                        piece_types(f3, a.F, a.nh, a.xh, a.induced, centre, (int32_t)k, u, w, lk,
+                                    (int)(a.vinfo[u] >> 26), (int)(a.vinfo[w] >> 26), by);
+                    types = matched_types(a.smp, types, (int32_t)k, u, w);
+                    keep = st_types(a.smp, a.n, types, (int32_t)k, u, w) != 0;
+                }
+            }
+            const int64_t ex = wave_excl(keep ? 1 : 0, lane);
+            if (off && keep) {
+                const int64_t x = off[k] + done + ex;
+                key[x] = (uint64_t)(uint32_t)min(u, w) << 32 | (uint32_t)max(u, w);
+                code[x] = (uint8_t)((centre ? 0u : 1u) | (u > w ? 2u : 0u));
+            }
+            done += wave_sum(keep ? 1 : 0);
+        }
+        if (!off && lane == 0) cnt[k] = done;
+    }
+}
+
 // Hash-table accounting (Section 6.2's memory-access comparison): the size
 // of every joining vertex's key group, the stored size-3 subgraphs that
 // contain it (one wave per vertex, lanes over its piece slots), and the sum
@@ -1806,7 +1847,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         uint64_t lkey = ~0ull;   // sorted lists: this lane's (min, max) key
         if (q < Q) {
             bool centre;
-            if (N == 5 && a.pkey) {
+            if ((N == 5 || EXTRA) && a.pkey) {
                 const int64_t x = a.poff[k] + q;
                 lkey = a.pkey[x];
                 const uint32_t cd = a.pcode[x];
@@ -2665,6 +2706,9 @@ struct Miner {
         return s;
     }
     void group_thresholds(int kind, int n, uint64_t cap, DBuf<uint64_t>& thr);
+    SelArgs sel_args(int n) const;
+    void st_pieces(int n, const Sampling& smp, DBuf<int64_t>& cnt, DBuf<int64_t>& off,
+                   DBuf<uint64_t>& key, DBuf<uint8_t>& code);
     void neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
                           DBuf<int32_t>& tab);
     DBuf<int64_t> npieces;
@@ -2907,6 +2951,7 @@ struct Miner {
         DBuf<int64_t> goff, gcnt, toff;
         int64_t ngroups = 0, ntiles = 0;
         int tile_p = TILE_P_MAX;
+        const int64_t* pieces = nullptr;   // candidates per joining vertex
     };
     void build_groups(const Level& P, int M, int64_t nwork, Groups& G,
                       const int64_t* pieces = nullptr);
@@ -3000,15 +3045,61 @@ void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32
 // kind SEL_MATCH (size-3 subgraphs credited to the vertex), SEL_PIECES
 // (stored size-3 subgraphs containing the joining vertex, size-n join) or
 // SEL_EDGES (its G_f edges at a size-n edge join); cap members per group.
-void Miner::group_thresholds(int kind, int n, uint64_t cap, DBuf<uint64_t>& thr) {
-    thr.alloc((size_t)g->n);
+SelArgs Miner::sel_args(int n) const {
     SelArgs a;
     a.row = frow.p; a.col = fcol.p; a.leafoff = leafoff.p; a.npieces = npieces.p;
     a.vinfo = vinfo.p; a.vg = g->vg; a.f3 = f3.p; a.F = F;
     a.nh = nh(); a.xh = xh();
     a.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
     a.smp = sampling();
-    a.n = n; a.groups = g->n; a.cap = cap; a.thr = thr.p;
+    a.n = n; a.groups = g->n; a.cap = 0; a.thr = nullptr;
+    return a;
+}
+
+// ST: every joining vertex's kept pieces at the size-n join as lists (key
+// order at size 5, as the join's size-5 filter needs); left empty (the join
+// then decodes and tests every piece) beyond 2^31 pieces.
+void Miner::st_pieces(int n, const Sampling& smp, DBuf<int64_t>& cnt, DBuf<int64_t>& off,
+                      DBuf<uint64_t>& key, DBuf<uint8_t>& code) {
+    const int64_t nv = g->n;
+    SelArgs a = sel_args(n);
+    a.smp = smp;
+    cnt.alloc((size_t)nv);
+    off.alloc((size_t)nv + 1);
+    k_st_pieces<<<grid_for(nv, TPB / 64), TPB, 0, st>>>(a, nullptr, cnt.p, nullptr, nullptr);
+    FSM_LAUNCH_CHECK();
+    const int64_t total = scan_exclusive(cnt.p, off.p, nv);
+    if (total >= (int64_t)INT32_MAX) {
+        cnt.reset();
+        off.reset();
+        return;
+    }
+    FSM_HIP(hipMemcpyAsync(off.p + nv, &total, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    const size_t len = (size_t)std::max<int64_t>(total, 1);
+    key.alloc(len);
+    code.alloc(len);
+    if (n != 5) {
+        k_st_pieces<<<grid_for(nv, TPB / 64), TPB, 0, st>>>(a, off.p, nullptr, key.p, code.p);
+        FSM_LAUNCH_CHECK();
+        return;
+    }
+    DBuf<uint64_t> k0(len);
+    DBuf<uint8_t> c0(len);
+    k_st_pieces<<<grid_for(nv, TPB / 64), TPB, 0, st>>>(a, off.p, nullptr, k0.p, c0.p);
+    FSM_LAUNCH_CHECK();
+    if (total > 0) {
+        DBuf<int32_t> off32((size_t)nv + 1);
+        k_offsets32<<<grid_for(nv + 1, TPB), TPB, 0, st>>>(off.p, nv + 1, off32.p);
+        FSM_LAUNCH_CHECK();
+        sort_segments(k0.p, key.p, c0.p, code.p, (int)total, (int)nv, off32.p);
+    }
+}
+
+void Miner::group_thresholds(int kind, int n, uint64_t cap, DBuf<uint64_t>& thr) {
+    thr.alloc((size_t)g->n);
+    SelArgs a = sel_args(n);
+    a.cap = cap;
+    a.thr = thr.p;
     const unsigned grid = grid_for(g->n, 1, 1u << 16);
     switch (kind) {
         case SEL_PIECES: k_group_select<SEL_PIECES><<<grid, SEL_TPB, 0, st>>>(a); break;
@@ -3064,6 +3155,7 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
                          const int64_t* pieces) {
     if (nwork > (int64_t)INT32_MAX * M)
         fail(FSM_EUNSUPPORTED, "more than 2^31-1 parent embeddings");
+    G.pieces = pieces ? pieces : npieces.p;
     const int64_t n = g->n;
     uint64_t cap = pow2_at_least((uint64_t)std::min<int64_t>(nwork, n * 16) * 2 + 16);
     DBuf<int32_t> wslot((size_t)nwork);
@@ -3120,7 +3212,7 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
     const int64_t want = (int64_t)tpw * grid_persistent * (TPB / 64);
     for (G.tile_p = TILE_P_MAX;; G.tile_p /= 2) {
         k_key_tiles<<<grid_for(G.ngroups, TPB), TPB, 0, st>>>(
-            G.gk.p, G.gcnt.p, pieces ? pieces : npieces.p, G.ngroups, G.tile_p, tiles.p);
+            G.gk.p, G.gcnt.p, G.pieces, G.ngroups, G.tile_p, tiles.p);
         FSM_LAUNCH_CHECK();
         G.ntiles = scan_exclusive(tiles.p, G.toff.p, G.ngroups);
         if (G.tile_p == 1 || G.ntiles >= want) break;
@@ -3143,7 +3235,7 @@ void Miner::order_groups(const Level& P, int M, const ItemRows& IR, const float*
                                                            rowcost.p);
     FSM_LAUNCH_CHECK();
     DBuf<int64_t> tiles((size_t)ng);
-    k_key_tiles<<<grid_for(ng, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p, ng, G.tile_p,
+    k_key_tiles<<<grid_for(ng, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, G.pieces, ng, G.tile_p,
                                                    tiles.p);
     FSM_LAUNCH_CHECK();
     DBuf<float> gcost((size_t)ng);
@@ -3171,7 +3263,7 @@ void Miner::order_groups(const Level& P, int M, const ItemRows& IR, const float*
     to_device(G.gk.p, pk.data(), (size_t)ng);
     to_device(G.goff.p, po.data(), (size_t)ng);
     to_device(G.gcnt.p, pn.data(), (size_t)ng);
-    k_key_tiles<<<grid_for(ng, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, npieces.p, ng, G.tile_p,
+    k_key_tiles<<<grid_for(ng, TPB), TPB, 0, st>>>(G.gk.p, G.gcnt.p, G.pieces, ng, G.tile_p,
                                                    tiles.p);
     FSM_LAUNCH_CHECK();
     const int64_t nt = scan_exclusive(tiles.p, G.toff.p, ng);
@@ -3321,13 +3413,7 @@ void Miner::join(int n) {
     // key group (capped at the ST sample)
     if (nwork > 0) {
         DBuf<int64_t> gsize((size_t)g->n);
-        SelArgs sa;
-        sa.row = frow.p; sa.col = fcol.p; sa.leafoff = leafoff.p; sa.npieces = npieces.p;
-        sa.vinfo = vinfo.p; sa.vg = g->vg; sa.f3 = f3.p; sa.F = F;
-        sa.nh = nh(); sa.xh = xh();
-        sa.induced = (opt.mode & FSM_INDUCED) ? 1 : 0;
-        sa.smp = sampling();
-        sa.n = n; sa.groups = g->n; sa.cap = 0; sa.thr = nullptr;
+        const SelArgs sa = sel_args(n);
         k_key_group_sizes<<<grid_for(g->n, TPB / 64), TPB, 0, st>>>(sa, gsize.p);
         FSM_LAUNCH_CHECK();
         DBuf<unsigned long long> hb(1);
@@ -3387,15 +3473,17 @@ void Miner::join(int n) {
 #undef FSM_JOIN_CASE
         FSM_LAUNCH_CHECK();
     };
+    // ST: the domain pass enumerates only each key group's sampled pieces
+    DBuf<int64_t> stcnt, poff;
+    DBuf<uint64_t> pkey;
+    DBuf<uint8_t> pcode;
+    if (smp.kthr && nwork > 0) st_pieces(n, smp, stcnt, poff, pkey, pcode);
     Groups G;
-    if (nwork > 0) build_groups(P, M, nwork, G);
+    if (nwork > 0) build_groups(P, M, nwork, G, stcnt.p);
     if (y.p && G.ntiles > 0 && opt.schedule == FSM_SCHEDULE_QUEUE) order_groups(P, M, IR, y.p, G);
     // size 5: pieces of every joining vertex sorted by their (min, max) key,
     // so that the pieces preceding a parent's triple are a prefix of a tile
-    DBuf<int64_t> poff;
-    DBuf<uint64_t> pkey;
-    DBuf<uint8_t> pcode;
-    if (n == 5 && G.ntiles > 0) sorted_pieces(poff, pkey, pcode);
+    if (n == 5 && G.ntiles > 0 && !stcnt.p) sorted_pieces(poff, pkey, pcode);
     const uint32_t dsize = 1u << (n * (n - 1) / 2);
     DBuf<uint16_t> dtab(dsize);
     k_dissect_table<<<grid_for(dsize, TPB), TPB, 0, st>>>(n, dtab.p);
@@ -3405,7 +3493,7 @@ void Miner::join(int n) {
         FSM_HIP(hipMemcpyAsync(drec.p, &hrec, sizeof(Rec), hipMemcpyHostToDevice, st));
         TileArgs t;
         t.row = frow.p; t.col = fcol.p; t.vinfo = vinfo.p; t.vg = g->vg;
-        t.npieces = npieces.p; t.leafoff = leafoff.p;
+        t.npieces = stcnt.p ? stcnt.p : npieces.p; t.leafoff = leafoff.p;
         t.nh = nh();
         t.f3 = f3.p; t.F = F;
         t.par = P.emb.p; t.padj = P.tab.qadj.p;
