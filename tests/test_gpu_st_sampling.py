@@ -176,3 +176,40 @@ def test_cl100k_thresholds_scored_against_exact():
         s = fsm.score_sampled(exact, r.patterns)
         assert s["lower_bound"] and s["precision"] == 1.0, s
         say(f"ST4 + matching 64: recall {s['recall']:.3f} by size {s['by_size']}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fixed_size_sampling_size7_matches_oracle(seed):
+    # ST 3 with matching 5 on 10 vertices: hundreds of sampled size-7
+    # subgraphs through two materialised joins
+    src, dst, lab = graph(7400 + seed, 10, 15, 3)
+    want, counts = sp.mine(10, src, dst, lab, 1, 7, join_threshold=3, match_threshold=5,
+                           seed=seed, with_counts=True)
+    assert counts[7] > 0
+    r = gpu(10, src, dst, lab, 1, 7, join_threshold=3, match_threshold=5, seed=seed)
+    assert r.patterns == want
+    assert produced(r, 7) == counts
+
+
+def test_learned_sizing_leaves_st_samples_unchanged():
+    # the cost model only sizes tables: with ST the results stay the sample's
+    src, dst, lab = graph(1500, 16, 34, 2)
+    with fsm.Graph(16, src, dst, lab) as g:
+        rec = fsm.mine(g, 2, 6, record=True)
+        with fsm.Model(fsm.FEATURES, seed=2) as m:
+            m.train(rec.train_x, rec.train_t, 100, 3e-3)
+            a = fsm.mine(g, 2, 6, fsm.FSM_LEARNED, model=m, join_threshold=2, seed=4)
+        b = fsm.mine(g, 2, 6, join_threshold=2, seed=4)
+    assert a.patterns == b.patterns == sp.mine(16, src, dst, lab, 2, 6, join_threshold=2, seed=4)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_single_vertex_induced_sampling_matches_oracle(seed):
+    src, dst, lab = graph(1600 + seed, 16, 32, 3)
+    for x in (1, 2):
+        want, counts = sp.mine_single(16, src, dst, lab, 2, 5, join_threshold=x, seed=seed,
+                                      induced=True, with_counts=True)
+        r = gpu(16, src, dst, lab, 2, 5, fsm.FSM_SINGLE | fsm.FSM_INDUCED, join_threshold=x,
+                seed=seed)
+        assert r.patterns == want
+        assert produced(r, 5) == counts
