@@ -31,11 +31,23 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.h"
 #include "internal.h"
 #include "model.h"
+
+// FSM_TRACE=1 in the environment: one line per domain pass and join level on
+// stderr (progress of long calls).
+static bool fsm_trace() {
+    static const bool on = [] {
+        const char* e = std::getenv("FSM_TRACE");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
 
 namespace fsm {
 namespace {
@@ -72,6 +84,9 @@ struct Pool {
     const int32_t* lrank;      // rank of each vertex among its label's vertices
     uint32_t W;                // words per bitmap in this pass
     int32_t rbase;             // this pass covers ranks rbase .. rbase + 32 W - 1
+    const int32_t* porb = nullptr;   // set: (slot s, position p) owns bitmap porb[s*n+p]
+                                     // (its pattern's orbit; -1: none)
+    unsigned long long* qcnt = nullptr;   // set: subgraphs recorded per QP slot
 };
 
 struct Rec {
@@ -200,16 +215,26 @@ __device__ __forceinline__ void set_bit_in(uint32_t* bm, int32_t r, int32_t rbas
     if (x < 32u * W) set_bit(bm, (int32_t)x);
 }
 
+// Bitmap of (QP slot s, position p) in this pass's pool, or null.
+__device__ __forceinline__ uint32_t* bitmap_at(const Pool& P, uint64_t s, int n, int p) {
+    if (P.porb) {
+        const int32_t x = P.porb[s * n + p];
+        return x < 0 ? nullptr : P.words + (uint64_t)x * P.W;
+    }
+    return P.words + (s * n + p) * P.W;
+}
+
 // Domain pass: record one subgraph; returns its QP slot (or -1).
 template <int N>
 __device__ __forceinline__ int64_t record(const Rec& R, uint64_t key, uint64_t L, uint64_t A,
                                           const int32_t (&v)[N]) {
     const int64_t s = qp_slot(R, key, L, A);
     if (s < 0) return -1;
-    uint32_t* base = R.pool.words + (uint64_t)s * N * R.pool.W;
+    if (R.pool.qcnt) atomicAdd(&R.pool.qcnt[s], 1ull);
 #pragma unroll
     for (int p = 0; p < N; ++p)
-        set_bit_in(base + (uint64_t)p * R.pool.W, R.pool.lrank[v[p]], R.pool.rbase, R.pool.W);
+        if (uint32_t* bm = bitmap_at(R.pool, (uint64_t)s, N, p))
+            set_bit_in(bm, R.pool.lrank[v[p]], R.pool.rbase, R.pool.W);
     return s;
 }
 
@@ -1612,6 +1637,8 @@ struct TileArgs {
     int induced;                // vertex-induced: induced pieces, C = E_c only
     NbrHash xh;                 // vertex-induced: edges outside G_f
     Sampling smp;               // matching and ST sampling thresholds
+    const int32_t* porb;        // as Pool::porb (EXTRA builds)
+    unsigned long long* qcnt;   // as Pool::qcnt (EXTRA builds)
 };
 
 constexpr uint32_t RANK_MASK = (1u << 26) - 1;
@@ -1762,7 +1789,23 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                         c.k0 = key; c.v0 = (uint64_t)s;
                     }
                 }
-                if (s >= 0) {
+                if (s >= 0 && EXTRA && (a.porb || a.qcnt)) {
+                    // candidate-bitmap passes: per-QP counts, bits in the
+                    // (pattern, orbit) bitmap of each position
+                    if (a.qcnt) atomicAdd(&a.qcnt[s], 1ull);
+                    const bool once = (uint64_t)s + 1 != c.b0 && (uint64_t)s + 1 != c.b1;
+#pragma unroll
+                    for (int p = 0; p < N; ++p) {
+                        if ((p >= M || p == i) && !once) continue;
+                        uint32_t* b = bitmap_at(Pool{a.bits, nullptr, a.W, a.rbase, a.porb},
+                                                (uint64_t)s, N, p);
+                        if (b) set_bit_in(b, lr[p], a.rbase, a.W);
+                    }
+                    if (once) {
+                        c.b1 = c.b0;
+                        c.b0 = (uint64_t)s + 1;
+                    }
+                } else if (s >= 0) {
                     const uint32_t W = a.W;
                     uint32_t* base = a.bits + (uint64_t)s * N * W;
                     // joining vertex and piece vertices: once per QP per tile
@@ -2014,6 +2057,8 @@ struct SingleTileArgs {
     const uint32_t* flags;
     unsigned long long* ctr;   // [emitted, candidates, tile counter, bytes]
     Sampling smp;              // ethr: this join's sampled neighbour lists
+    const int32_t* porb;       // as Pool::porb
+    unsigned long long* qcnt;  // as Pool::qcnt
 };
 
 template <int N>
@@ -2159,18 +2204,25 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                             }
                         }
                         if (sl >= 0) {
-                            uint32_t* base = a.bits + (uint64_t)sl * N * a.W;
+                            if (a.qcnt) atomicAdd(&a.qcnt[sl], 1ull);
+                            auto bm = [&](int p) -> uint32_t* {
+                                if (a.porb) {
+                                    const int32_t x = a.porb[(uint64_t)sl * N + p];
+                                    return x < 0 ? nullptr : a.bits + (uint64_t)x * a.W;
+                                }
+                                return a.bits + ((uint64_t)sl * N + p) * a.W;
+                            };
                             // k and u: once per QP per tile
                             if ((uint64_t)sl + 1 != c.b0 && (uint64_t)sl + 1 != c.b1) {
-                                set_bit_in(base + (uint64_t)i * a.W, lr[i], a.rbase, a.W);
-                                set_bit_in(base + (uint64_t)M * a.W, lr[M], a.rbase, a.W);
+                                if (uint32_t* b = bm(i)) set_bit_in(b, lr[i], a.rbase, a.W);
+                                if (uint32_t* b = bm(M)) set_bit_in(b, lr[M], a.rbase, a.W);
                                 c.b1 = c.b0;
                                 c.b0 = (uint64_t)sl + 1;
                             }
 #pragma unroll
                             for (int j = 0; j < M; ++j) {
                                 if (j == i) continue;
-                                set_bit_in(base + (uint64_t)j * a.W, lr[j], a.rbase, a.W);
+                                if (uint32_t* b = bm(j)) set_bit_in(b, lr[j], a.rbase, a.W);
                             }
                         }
                         ++got;
@@ -2334,6 +2386,92 @@ __global__ void k_mni(MniArgs a, const int64_t* ocnt) {
             a.out_key[idx] = key;
             a.out_sup[idx] = best;
         }
+    }
+}
+
+// Levels whose domains take more than one rank slice keep bitmaps only for
+// candidate patterns.  The automorphisms of a subgraph map an orbit o onto
+// itself, so every subgraph puts exactly |o| vertices into o's domain and a
+// pattern's MNI support is at most (its subgraph count) x (its smallest
+// orbit's size); a pattern below t on that bound is infrequent.  Its support
+// from the first slice is a lower bound below t; the later slices set bits
+// directly in one bitmap per candidate (pattern, orbit).
+__global__ void k_pattern_counts(QPTab q, uint64_t slots, const unsigned long long* qcnt,
+                                 unsigned long long* pcnt) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        if (q.kv[2 * s] == EMPTY_KEY || !(q.kv[2 * s + 1] & VALID)) continue;
+        if (qcnt[s]) atomicAdd(&pcnt[q.pat[s]], qcnt[s]);
+    }
+}
+
+// cand[s*n+o] = 1 for the orbit representatives o of candidate pattern slots.
+__global__ void k_candidate_flags(CodeTab c, uint64_t slots, int n,
+                                  const unsigned long long* pcnt, const int64_t* tg,
+                                  int64_t* cand) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < slots * n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t s = x / n;
+        const int p = (int)(x - s * n);
+        int64_t f = 0;
+        const uint64_t key = c.kv[2 * s];
+        if (key != EMPTY_KEY) {
+            const uint64_t info = c.info[s];
+            if ((info & VALID) && (int)((info >> (3 * p)) & 7u) == p) {
+                int smallest = n;   // smallest orbit size
+                for (int r = 0; r < n; ++r) {
+                    if ((int)((info >> (3 * r)) & 7u) != r) continue;
+                    int size = 0;
+                    for (int q = 0; q < n; ++q) size += (int)((info >> (3 * q)) & 7u) == r;
+                    smallest = min(smallest, size);
+                }
+                if (pcnt[s] * (unsigned long long)smallest >=
+                    (unsigned long long)tg[code_graph(key, n)])
+                    f = 1;
+            }
+        }
+        cand[x] = f;
+    }
+}
+
+__global__ void k_po_map(const int64_t* cand, const int64_t* poidx, uint64_t items,
+                         int64_t* pomap) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < items;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        if (cand[x]) pomap[poidx[x]] = (int64_t)x;
+}
+
+// porb[s*n+p]: the candidate (pattern, orbit) bitmap of QP slot s's
+// position p, or -1.
+__global__ void k_qp_orbit_map(QPTab q, uint64_t slots, int n, const int64_t* cand,
+                               const int64_t* poidx, int32_t* porb) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < slots * n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t s = x / n;
+        const int p = (int)(x - s * n);
+        int32_t r = -1;
+        const uint64_t v = q.kv[2 * s + 1];
+        if (q.kv[2 * s] != EMPTY_KEY && (v & VALID)) {
+            const uint64_t y = (uint64_t)q.pat[s] * n + ((v >> (3 * p)) & 7u);
+            if (cand[y]) r = (int32_t)poidx[y];
+        }
+        porb[x] = r;
+    }
+}
+
+// Popcount of every candidate bitmap of a direct slice into its orbit's
+// domain size; one wavefront per bitmap.
+__global__ __launch_bounds__(TPB) void k_dense_count(const uint32_t* words, uint64_t nbm,
+                                                     uint32_t W, const int64_t* pomap,
+                                                     int64_t* ocnt) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nw = (uint64_t)gridDim.x * (TPB / 64);
+    for (uint64_t b = (uint64_t)wave_id_global(); b < nbm; b += nw) {
+        const uint32_t* bm = words + b * W;
+        int64_t cnt = 0;
+        for (uint32_t i = lane; i < W; i += 64) cnt += __popc(bm[i]);
+        cnt = wave_sum(cnt);
+        if (lane == 0 && cnt) ocnt[pomap[b]] += cnt;
     }
 }
 
@@ -2718,7 +2856,9 @@ struct Miner {
     uint64_t pool_words = 0, ppool_words = 0;
     uint64_t pool_budget = 0;     // bytes for the QP and pattern bitmap pools
     uint32_t pass_W = 0;          // current domain pass: words per bitmap,
-    int32_t pass_rbase = 0;       // first rank of its slice
+    int32_t pass_rbase = 0;       // first rank of its slice,
+    const int32_t* pass_porb = nullptr;        // its candidate bitmap map,
+    unsigned long long* pass_qcnt = nullptr;   // its per-QP subgraph counts
     DBuf<int32_t> lrank;
     DBuf<uint32_t> vinfo;
     DBuf<Rec> drec;     // device copy of the recording context of the join
@@ -2755,7 +2895,7 @@ struct Miner {
         R.q = {L.tab.qkv.p, L.tab.qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p,
                L.tab.qcount.p};
         R.c = {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
-        R.pool = {pool.p, lrank.p, pass_W, pass_rbase};
+        R.pool = {pool.p, lrank.p, pass_W, pass_rbase, pass_porb, pass_qcnt};
         R.flags = flags.p;
         R.n = L.n;
         return R;
@@ -2790,6 +2930,7 @@ struct Miner {
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
         uint64_t qcap = L.tab.qcap ? L.tab.qcap : std::max(qcap0(), qhint[L.n]);
+        DBuf<unsigned long long> qcnt;
         const int64_t ranks = (int64_t)W * 32;
         uint32_t w0 = W;
         for (int attempt = 0;; ++attempt) {
@@ -2804,10 +2945,21 @@ struct Miner {
             pass_W = w0;
             pass_rbase = 0;
             ensure_pool(pool, pool_words, qcap * (uint64_t)L.n * w0);
+            // more slices to come: count the subgraphs of every QP
+            if ((int64_t)w0 * 32 < ranks) {
+                qcnt.alloc(qcap);
+                qcnt.zero();
+                pass_qcnt = qcnt.p;
+            }
             counters.zero();
             flags.zero();
             launch(rec(L), 0);
+            pass_qcnt = nullptr;
             const uint32_t f = scalar_to_host(flags.p);
+            if (fsm_trace())
+                std::fprintf(stderr, "[fsm] size %d pass 0 attempt %d: qp capacity %llu, "
+                             "%u of %u words, flags %u\n", L.n, attempt,
+                             (unsigned long long)qcap, w0, W, f);
             if (f & (ERR_MISSING | ERR_FILL))
                 fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", L.n, f);
             if (!(f & OVF_QP)) break;
@@ -2873,6 +3025,29 @@ struct Miner {
             }
         };
         reduce_slice(w0);
+        // more slices to come: candidate patterns (subgraphs x n >= t) and a
+        // dense index of their (pattern, orbit) bitmaps
+        DBuf<int64_t> cand, poidx, pomap;
+        int64_t npo = -1;
+        if ((int64_t)w0 * 32 < ranks) {
+            DBuf<unsigned long long> pcnt(ccap);
+            pcnt.zero();
+            k_pattern_counts<<<grid_for((int64_t)qcap, TPB), TPB, 0, st>>>(q, qcap, qcnt.p, pcnt.p);
+            FSM_LAUNCH_CHECK();
+            const uint64_t items = ccap * (uint64_t)L.n;
+            cand.alloc(items);
+            poidx.alloc(items);
+            k_candidate_flags<<<grid_for((int64_t)items, TPB), TPB, 0, st>>>(ct, ccap, L.n, pcnt.p,
+                                                                            dtg.p, cand.p);
+            FSM_LAUNCH_CHECK();
+            npo = scan_exclusive(cand.p, poidx.p, (int64_t)items);
+            if (npo >= (int64_t)INT32_MAX)
+                fail(FSM_EUNSUPPORTED, "more than 2^31 candidate orbit domains at size %d", L.n);
+            pomap.alloc((size_t)std::max<int64_t>(npo, 1));
+            k_po_map<<<grid_for((int64_t)items, TPB), TPB, 0, st>>>(cand.p, poidx.p, items, pomap.p);
+            FSM_LAUNCH_CHECK();
+            qcnt.reset();
+        }
         // more slices to come: move the QPs into a table sized for them
         // (an overflow rerun grows the table 16-fold), so that every later
         // slice can be wider
@@ -2895,7 +3070,39 @@ struct Miner {
             }
         }
         int slices = 1;
-        for (int64_t lo = (int64_t)w0 * 32; lo < ranks; ++slices) {
+        if (npo >= 0) {
+            // direct slices: bits go straight into the candidate bitmaps
+            DBuf<int32_t> porb((size_t)qcap * L.n);
+            k_qp_orbit_map<<<grid_for((int64_t)(qcap * L.n), TPB), TPB, 0, st>>>(
+                q, qcap, L.n, cand.p, poidx.p, porb.p);
+            FSM_LAUNCH_CHECK();
+            const uint64_t per_word = (uint64_t)std::max<int64_t>(npo, 1) * sizeof(uint32_t);
+            for (int64_t lo = (int64_t)w0 * 32; npo > 0 && lo < ranks; ++slices) {
+                const uint32_t wr = (uint32_t)std::max<uint64_t>(
+                    1, std::min<uint64_t>((uint64_t)(ranks - lo + 31) / 32,
+                                          pool_budget / 2 / per_word));
+                pass_W = wr;
+                pass_rbase = (int32_t)lo;
+                pass_porb = porb.p;
+                ensure_pool(pool, pool_words, (uint64_t)npo * wr);
+                counters.zero();
+                flags.zero();
+                launch(rec(L), slices);
+                pass_porb = nullptr;
+                const uint32_t f = scalar_to_host(flags.p);
+                if (f) fail(FSM_EDEVICE, "domain slice %d of size %d failed (flags %u)", slices, L.n, f);
+                k_dense_count<<<grid_for(npo, TPB / 64, 1u << 16), TPB, 0, st>>>(
+                    pool.p, (uint64_t)npo, wr, pomap.p, ocnt.p);
+                FSM_LAUNCH_CHECK();
+                lo += (int64_t)wr * 32;
+                if (fsm_trace())
+                    std::fprintf(stderr, "[fsm] size %d direct slice %d: %u words, ranks up to "
+                                 "%lld of %lld, %lld candidate orbit bitmaps of %u patterns\n",
+                                 L.n, slices, wr, (long long)lo, (long long)ranks,
+                                 (long long)npo, npat);
+            }
+        }
+        for (int64_t lo = (int64_t)w0 * 32; npo < 0 && lo < ranks; ++slices) {
             const uint32_t wr = slice_words(qcap, L.n);
             pass_W = wr;
             pass_rbase = (int32_t)lo;
@@ -2907,6 +3114,10 @@ struct Miner {
             if (f) fail(FSM_EDEVICE, "domain slice %d of size %d failed (flags %u)", slices, L.n, f);
             reduce_slice(wr);
             lo += (int64_t)wr * 32;
+            if (fsm_trace())
+                std::fprintf(stderr, "[fsm] size %d slice %d: %u words, ranks up to %lld of "
+                             "%lld, %u QPs, %u patterns\n", L.n, slices, wr, (long long)lo,
+                             (long long)ranks, nqp, npat);
         }
         L.st.rank_slices = slices;
         pass_W = W;
@@ -3371,6 +3582,9 @@ void Miner::join(int n) {
     const int64_t nwork = P.rows * M;
     L.st.parents = P.rows;
     L.st.work_items = nwork;
+    if (fsm_trace())
+        std::fprintf(stderr, "[fsm] size %d join: %lld parents, %lld work items\n", n,
+                     (long long)P.rows, (long long)nwork);
     // cost-model work items: predictions size the QP table; recorded
     // targets come from the domain pass
     const bool learned = (opt.mode & FSM_LEARNED) && model != nullptr;
@@ -3502,6 +3716,7 @@ void Miner::join(int n) {
         t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p;
         t.tile_p = G.tile_p;
         t.bits = R.pool.words; t.W = R.pool.W; t.rbase = R.pool.rbase; t.rec = drec.p;
+        t.porb = R.pool.porb; t.qcnt = R.pool.qcnt;
         t.flags = R.flags;
         t.item_children = nullptr;
         t.pkey = pkey.p;
@@ -3519,7 +3734,7 @@ void Miner::join(int n) {
         return t;
     };
     // the plain exact join runs a build of the tile kernel without the
-    // sampling and vertex-induced paths
+    // sampling, vertex-induced and candidate-bitmap paths
     const bool extra = (opt.mode & (FSM_SAMPLED | FSM_INDUCED)) || ithr.p || smp.kthr ||
                        smp.ethr || smp.mthr;
     hipEvent_t j0, j1;
@@ -3539,9 +3754,10 @@ void Miner::join(int n) {
             if (G.ntiles > 0) {
                 TileArgs t = tile_args(R);
                 t.item_children = pass == 0 ? ich.p : nullptr;
+                const bool ex = extra || t.porb || t.qcnt;
 #define FSM_TILES_CASE(NN)                                                          \
     case NN:                                                                        \
-        if (extra) k_join_tiles<NN, true><<<grid_persistent, TPB, 0, st>>>(t);       \
+        if (ex) k_join_tiles<NN, true><<<grid_persistent, TPB, 0, st>>>(t);          \
         else k_join_tiles<NN, false><<<grid_persistent, TPB, 0, st>>>(t);            \
         break;
                 switch (n) {
@@ -3670,6 +3886,7 @@ void Miner::join_single(int n) {
         t.ngroups = G.ngroups; t.ntiles = G.ntiles; t.glist = G.glist.p; t.tile_p = G.tile_p;
         t.svtab = svtab.p;
         t.bits = R.pool.words; t.W = R.pool.W; t.rbase = R.pool.rbase; t.rec = drec.p;
+        t.porb = R.pool.porb; t.qcnt = R.pool.qcnt;
         t.flags = R.flags;
         t.ctr = counters.p;
         t.smp = smp;
@@ -3877,6 +4094,12 @@ void Miner::run() {
             if (opt.max_size < 5) lv[3].tab = Tables();
             for (int n = 4; n <= opt.max_size; ++n) {
                 timed(n, [&] { join(n); });
+                if (fsm_trace())
+                    std::fprintf(stderr, "[fsm] size %d done: %lld children, %lld QPs, "
+                                 "%lld patterns, %lld slices, %.1f ms\n", n,
+                                 (long long)lv[n].st.emitted, (long long)lv[n].st.quick_patterns,
+                                 (long long)lv[n].st.patterns, (long long)lv[n].st.rank_slices,
+                                 lv[n].st.kernel_ms);
                 // size n-2 embeddings and their QP table are no longer needed,
                 // nor the size-n table when no later join reads it
                 lv[n - 2].emb.reset();
