@@ -256,9 +256,12 @@ def _match_unit(T):
 
 
 def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_threshold=0,
-         match_threshold=0, seed=0, induced=False, prune=True, with_counts=False):
+         match_threshold=0, seed=0, induced=False, prune=True, with_counts=False,
+         with_stored=False):
     """Frequent patterns (``oracle.mine``'s format) of the sampled join, and,
-    with ``with_counts``, the number of subgraphs produced at each size >= 3.
+    with ``with_counts``, the number of subgraphs produced at each size >= 3;
+    ``with_stored`` also returns the stored subgraphs of every size (size ->
+    set of (vertex set, edge set)).
 
     rate            keep probability of a key group's member (rate sampling)
     join_threshold  ST x: x^2 size-3 subgraphs per key group at every join,
@@ -357,6 +360,8 @@ def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_thr
             out.append(((size, labs, bits), (size, labs, adjbits, L.support[(labs, bits)])))
     out.sort(key=lambda x: x[0])
     res = [x[1] for x in out]
+    if with_stored:
+        return res, counts, {k: L.stored for k, L in levels.items()}
     return (res, counts) if with_counts else res
 
 
@@ -375,7 +380,7 @@ def removal(S):
 
 
 def mine_single(n_vertices, src, dst, labels, support, max_size, *, join_threshold=0,
-                seed=0, induced=False, with_counts=False):
+                seed=0, induced=False, with_counts=False, with_stored=False):
     """Single-vertex exploration (the baseline of Section 6): every size-n
     subgraph S is the size-(n-1) subgraph S - v joined with the edge (k, v)
     of the removal rule (v, k) above, plus the other edges of v into S - v.
@@ -422,4 +427,6 @@ def mine_single(n_vertices, src, dst, labels, support, max_size, *, join_thresho
             out.append(((size, labs, bits), (size, labs, adjbits, L.support[(labs, bits)])))
     out.sort(key=lambda x: x[0])
     res = [x[1] for x in out]
+    if with_stored:
+        return res, counts, {k: L.stored for k, L in levels.items()}
     return (res, counts) if with_counts else res
