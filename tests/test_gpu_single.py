@@ -117,3 +117,42 @@ def test_golden_single_vs_two_vertex(stem):
         assert sv.stats["levels"][n]["hash_bytes"] == 8 * sv.stats["levels"][n]["candidates"]
     for n in range(4, smax + 1):
         assert 0 < tv.stats["levels"][n]["hash_bytes"] <= 12 * tv.stats["levels"][n]["candidates"]
+
+
+def hash_bytes_two_vertex(stored, n, cap):
+    # 12 bytes per stored size-3 subgraph containing the joining vertex, for
+    # every (stored parent, position) work item, at most the ST sample
+    group = {}
+    for T in stored[3]:
+        for k in T[0]:
+            group[k] = group.get(k, 0) + 1
+    return sum(12 * min(group.get(k, 0), cap) for P in stored[n - 2] for k in P[0])
+
+
+def hash_bytes_single_vertex(stored, n, cap):
+    deg = {}
+    for P in stored[2]:
+        for k in P[0]:
+            deg[k] = deg.get(k, 0) + 1
+    return sum(8 * min(deg.get(k, 0), cap) for P in stored[n - 1] for k in P[0])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_hash_bytes_match_stored_key_groups(seed):
+    # the accounting of both explorations against the oracle's stored
+    # subgraphs: exact and with ST 2 (groups capped at 4 and 2)
+    src, dst, lab = graph(1700 + seed, 16, 32, 2)
+    big = 1 << 40
+    for x in (0, 2):
+        _, _, st = sp.mine(16, src, dst, lab, 2, 5, join_threshold=x, seed=seed,
+                           with_stored=True)
+        r = gpu(16, src, dst, lab, 2, 5, mode=0, join_threshold=x, seed=seed)
+        for n in (4, 5):
+            want = hash_bytes_two_vertex(st, n, x * x if x else big)
+            assert r.stats["levels"][n]["hash_bytes"] == want, (x, n)
+        _, _, st = sp.mine_single(16, src, dst, lab, 2, 5, join_threshold=x, seed=seed,
+                                  with_stored=True)
+        r = gpu(16, src, dst, lab, 2, 5, join_threshold=x, seed=seed)
+        for n in (3, 4, 5):
+            want = hash_bytes_single_vertex(st, n, x if x else big)
+            assert r.stats["levels"][n]["hash_bytes"] == want, (x, n)
