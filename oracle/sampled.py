@@ -257,11 +257,11 @@ def _match_unit(T):
 
 def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_threshold=0,
          match_threshold=0, seed=0, induced=False, prune=True, with_counts=False,
-         with_stored=False):
+         with_stored=False, with_produced=False):
     """Frequent patterns (``oracle.mine``'s format) of the sampled join, and,
     with ``with_counts``, the number of subgraphs produced at each size >= 3;
-    ``with_stored`` also returns the stored subgraphs of every size (size ->
-    set of (vertex set, edge set)).
+    ``with_stored`` (``with_produced``) also returns the stored (produced)
+    subgraphs of every size: size -> set of (vertex set, edge set).
 
     rate            keep probability of a key group's member (rate sampling)
     join_threshold  ST x: x^2 size-3 subgraphs per key group at every join,
@@ -299,9 +299,11 @@ def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_thr
                 kept3.append(T)
     else:
         kept3 = cands3
+    made = {2: set(levels[2].code)}
     if max_size >= 3:
         levels[3] = _Level(kept3, labels, support)
         counts[3] = len(kept3)
+        made[3] = set(kept3)
     rthr = None
     if rate is not None:
         rthr = M64 if rate >= 1.0 else int(math.ldexp(rate, 64))
@@ -353,6 +355,7 @@ def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_thr
             produced.append(S)
         levels[size] = _Level(produced, labels, support)
         counts[size] = len(produced)
+        made[size] = set(produced)
     out = []
     for size, L in levels.items():
         for (labs, bits) in L.frequent:
@@ -360,6 +363,8 @@ def mine(n_vertices, src, dst, labels, support, max_size, *, rate=None, join_thr
             out.append(((size, labs, bits), (size, labs, adjbits, L.support[(labs, bits)])))
     out.sort(key=lambda x: x[0])
     res = [x[1] for x in out]
+    if with_produced:
+        return res, counts, made
     if with_stored:
         return res, counts, {k: L.stored for k, L in levels.items()}
     return (res, counts) if with_counts else res

@@ -227,3 +227,25 @@ def test_single_vertex_sampling_is_a_nested_lower_bound(seed):
             assert all(k in got and s <= got[k] for k, s in prev.items())
         prev = got
     assert as_map(sp.mine_single(16, src, dst, lab, 2, 5, join_threshold=64, seed=seed)) == exact
+
+
+def test_pruning_worked_example():
+    # Section 4.5's example: joining '012' and '234' at vertex 2 with the
+    # connecting edges 0-3 and 1-4 forms the triangles '023' and '124'.
+    # Labels A..E on 0..4; a second copy (5..9) lacks the edge 5-8, and an
+    # extra A-D edge (10-11) keeps every labelled edge frequent at t = 2, so
+    # triangle BCE (124) is frequent and ACD (023) is not: the combined
+    # subgraph is pruned, and the result does not change.
+    edges = [(0, 2), (1, 2), (2, 3), (2, 4), (0, 3), (1, 4),
+             (5, 7), (6, 7), (7, 8), (7, 9), (6, 9), (10, 11)]
+    src = np.array([a for a, _ in edges], np.int32)
+    dst = np.array([b for _, b in edges], np.int32)
+    lab = np.array([0, 1, 2, 3, 4, 0, 1, 2, 3, 4, 0, 3], np.int32)
+    S = (frozenset(range(5)), frozenset(edges[:6]))
+    assert sp.dissect(S) == (frozenset({0, 1, 2}), 2)   # '012' joined with '234' at 2
+    res_p, _, made_p = sp.mine(12, src, dst, lab, 2, 5, with_produced=True)
+    res_n, _, made_n = sp.mine(12, src, dst, lab, 2, 5, prune=False, with_produced=True)
+    assert S in made_n[5] and S not in made_p[5]
+    assert res_p == res_n == oracle.mine(12, src, dst, lab, 2, 5)
+    tri = {(n, labs, adj): sup for n, labs, adj, sup in res_p if n == 3 and adj == 7}
+    assert tri == {(3, (1, 2, 4), 7): 2}   # BCE frequent, ACD absent
