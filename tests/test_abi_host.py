@@ -289,3 +289,63 @@ def test_size5_parent_triple_bounds_the_accepted_piece():
             assert key(piece) < key(parent), (ids, edges)
             checked += 1
     assert checked == 728 * 3
+
+
+def _nbr_masks(n, adj):
+    nb = [0] * n
+    k = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            if adj >> k & 1:
+                nb[i] |= 1 << j
+                nb[j] |= 1 << i
+            k += 1
+    return nb
+
+
+def _connected_mask(S, nb):
+    if not S:
+        return False
+    seen = S & -S
+    while True:
+        grow = seen
+        x = seen
+        while x:
+            b = x & -x
+            grow |= nb[b.bit_length() - 1] & S
+            x ^= b
+        if grow == seen:
+            return seen == S
+        seen = grow
+
+
+def _check_split(n, adj, L):
+    # Theorem 1: every connected graph splits into a connected triple l and a
+    # connected rest (V \ l) + v' sharing one vertex v' of l
+    import ctypes
+    lm, sh = ctypes.c_uint32(), ctypes.c_int32()
+    ids = (ctypes.c_int32 * n)(*range(n))
+    nb = _nbr_masks(n, adj)
+    full = (1 << n) - 1
+    rc = L.fsm_dissect(n, ids, ctypes.c_uint32(adj), ctypes.byref(lm), ctypes.byref(sh))
+    if not _connected_mask(full, nb):
+        assert rc != 0
+        return False
+    assert rc == 0, adj
+    l, v = lm.value, sh.value
+    assert bin(l).count("1") == 3 and l >> v & 1
+    assert _connected_mask(l, nb) and _connected_mask((full & ~l) | (1 << v), nb), adj
+    return True
+
+
+def test_theorem1_every_connected_six_vertex_graph_splits():
+    L = fsm.lib()
+    got = sum(_check_split(6, adj, L) for adj in range(1 << 15))
+    assert got == 26704   # connected labelled graphs on 6 vertices
+
+
+def test_theorem1_seven_vertex_sample_splits():
+    L = fsm.lib()
+    rng = np.random.default_rng(77)
+    got = sum(_check_split(7, int(adj), L) for adj in rng.integers(0, 1 << 21, 20000))
+    assert got > 15000
