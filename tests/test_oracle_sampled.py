@@ -249,3 +249,27 @@ def test_pruning_worked_example():
     assert res_p == res_n == oracle.mine(12, src, dst, lab, 2, 5)
     tri = {(n, labs, adj): sup for n, labs, adj, sup in res_p if n == 3 and adj == 7}
     assert tri == {(3, (1, 2, 4), 7): 2}   # BCE frequent, ACD absent
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_induced_matching_keeps_t_per_vertex(seed):
+    # vertex-induced, t = 1: a vertex set {c, u, w} with u, w neighbours of c
+    # is a triangle (credited to its smallest vertex) when u ~ w, else a
+    # wedge credited to c; each vertex keeps min(t_m, credited)
+    src, dst, lab = graph(90 + seed, 14, 26, 2)
+    adj = {v: set() for v in range(14)}
+    for a, b in zip(src, dst):
+        adj[int(a)].add(int(b))
+        adj[int(b)].add(int(a))
+    credited = {}
+    for c in range(14):
+        for u, w in itertools.combinations(sorted(adj[c]), 2):
+            if w in adj[u]:
+                if c < u:
+                    credited[c] = credited.get(c, 0) + 1
+            else:
+                credited[c] = credited.get(c, 0) + 1
+    for tm in (1, 3):
+        _, counts = sp.mine(14, src, dst, lab, 1, 3, match_threshold=tm, seed=seed,
+                            induced=True, with_counts=True)
+        assert counts[3] == sum(min(tm, x) for x in credited.values())
