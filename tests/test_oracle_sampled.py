@@ -273,3 +273,35 @@ def test_induced_matching_keeps_t_per_vertex(seed):
         _, counts = sp.mine(14, src, dst, lab, 1, 3, match_threshold=tm, seed=seed,
                             induced=True, with_counts=True)
         assert counts[3] == sum(min(tm, x) for x in credited.values())
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("induced", [False, True])
+def test_support_bounded_by_subgraphs_times_smallest_orbit(seed, induced):
+    # the bound behind the candidate-pattern filter of sliced domain passes:
+    # every subgraph puts exactly |o| vertices into orbit o's domain, so
+    # MNI support <= subgraphs x smallest orbit size (equality is possible)
+    src, dst, lab = graph(110 + seed, 12, 20, 1 + seed % 2)
+    _, _, made = sp.mine(12, src, dst, lab, 1, 5, induced=induced, prune=False,
+                         with_produced=True)
+    labels = [int(x) for x in lab]
+    tight = 0
+    for size in (3, 4, 5):
+        count, dom, smallest = {}, {}, {}
+        for S in made[size]:
+            code, orders = sp._canon(S, labels)
+            count[code] = count.get(code, 0) + 1
+            d = dom.setdefault(code, [set() for _ in range(size)])
+            for order in orders:
+                for p, v in enumerate(order):
+                    d[p].add(v)
+            # orbit of position p: the positions that some canonical order
+            # maps to the vertex the first order puts at p
+            orbit = [sum(1 for q in range(size) if any(o[q] == orders[0][p] for o in orders))
+                     for p in range(size)]
+            smallest[code] = min(orbit)
+        for code, d in dom.items():
+            sup = min(len(x) for x in d)
+            assert sup <= count[code] * smallest[code], (size, code)
+            tight += sup == count[code] * smallest[code]
+    assert tight > 0
