@@ -65,12 +65,54 @@ def profiled_counters(size, workload):
     return vals
 
 
+def join_roofline(results, dom, workload):
+    """Roofline of the dominant kernel, the size-`dom` join's domain pass.
+
+    The pass probes hash tables and sets bits in bitmaps that L2 holds (98%
+    hit rate), so it is bound by vector-instruction issue, not HBM: bound
+    "alu", achieved = wave64 VALU instructions per launch (rocprofv3
+    SQ_INSTS_VALU, profiles/, taken on the current kernel sources) over the
+    launch's HIP-event duration, peak = the issue rate of 256 CUs x 4 SIMDs
+    at 2.4 GHz, one wave64 VALU instruction per 4 cycles per SIMD.  HBM
+    traffic (FETCH_SIZE + WRITE_SIZE, calibrated) over the same duration is
+    reported beside it against 8 TB/s, and the algorithmic bytes of the pass
+    (served from L2) as an L2-level rate."""
+    levels = results[0].stats["levels"]
+    ms = sum(r.stats["levels"][dom]["join_ms"] for r in results) / len(results)
+    nbytes = levels[dom]["algorithmic_bytes"]
+    sec = ms / 1e3
+    prof = profiled_counters(dom, workload)
+    kernel = f"k_join_tiles<{dom}, false> (domain pass)"
+    l2 = {"algorithmic_bytes": nbytes,
+          "achieved_GBs": round(nbytes / sec / 1e9, 3) if sec > 0 else None,
+          "note": "bytes the method must move; L2 serves them"}
+    if prof is None or not prof.get("SQ_INSTS_VALU") or sec <= 0:
+        return {"bound": "alu", "achieved": None, "peak": VALU_PEAK_WAVE_INSTS / 1e9,
+                "unit": "G wave64 VALU instructions/s", "frac": None, "traffic": None,
+                "kernel": kernel, "kernel_ms": round(ms, 3), "l2_level": l2,
+                "note": "no counter profile of the current kernel sources in profiles/"}
+    rate = prof["SQ_INSTS_VALU"] / sec
+    traffic = prof.get("traffic_bytes_per_launch")
+    hbm = None
+    if traffic:
+        hbm = {"achieved_GBs": round(traffic / sec / 1e9, 3), "peak_GBs": HBM_PEAK_GBS,
+               "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 6)}
+    return {"bound": "alu", "achieved": round(rate / 1e9, 3),
+            "peak": round(VALU_PEAK_WAVE_INSTS / 1e9, 3),
+            "unit": "G wave64 VALU instructions/s", "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
+            "traffic": traffic, "kernel": kernel, "kernel_ms": round(ms, 3),
+            "valu_wave_insts_per_launch": prof["SQ_INSTS_VALU"],
+            "hbm": hbm, "l2_level": l2}
+
+
 def batch_comparison(fsm, synth):
-    """The 256-graph workload mined two ways on the same device: plain
-    per-graph fsm_mine calls, and batched+learned (union passes with the
-    chunk size and tile height the autotuner picked on a 16-graph sample,
-    join tables sized and tiles ordered by a cost model that a warm-up batch
-    trained online).  Both must return identical results."""
+    """The 256-graph workload mined three ways on the same device: plain
+    per-graph fsm_mine calls; batched with plain table sizing (union passes
+    with the chunk size and tile height the autotuner picked on a 16-graph
+    sample); and batched+learned (the same, with join tables sized and tiles
+    ordered by a cost model trained online on a DISJOINT batch of the same
+    shape, seeds 4000+g, so the timed batch is held out).  All three must
+    return identical results."""
     import torch
     ws = synth.batch_workload()
     graphs = [fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"]) for w in ws]
@@ -79,11 +121,15 @@ def batch_comparison(fsm, synth):
     print(f"[bench] batch workload: {len(ws)} graphs, {sum(w['n'] for w in ws)} vertices",
           file=sys.stderr, flush=True)
     fsm.mine(graphs[0], sup[0], smax)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain = [fsm.mine(g, s, smax) for g, s in zip(graphs, sup)]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    plain, t_plain = timed(lambda: [fsm.mine(g, s, smax) for g, s in zip(graphs, sup)])
     print(f"[bench] plain per-graph: {t_plain:.3f} s", file=sys.stderr, flush=True)
     # autotuned shapes: every 16th graph as the sample
     t0 = time.perf_counter()
@@ -91,44 +137,118 @@ def batch_comparison(fsm, synth):
     t_tune = time.perf_counter() - t0
     print(f"[bench] tuned on {len(graphs[::16])} graphs in {t_tune:.1f} s: {tuned}",
           file=sys.stderr, flush=True)
+    bplain, t_bplain = timed(lambda: fsm.mine_batch(graphs, sup, smax, fsm.FSM_BATCHED))
+    print(f"[bench] batched, plain sizing: {t_bplain:.3f} s", file=sys.stderr, flush=True)
+    # the cost model learns on a disjoint batch of the same shape
+    train_ws = synth.batch_workload(seed=4000)
+    tgraphs = [fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"]) for w in train_ws]
     model = fsm.Model(fsm.FEATURES, seed=1)
     mode = fsm.FSM_BATCHED | fsm.FSM_LEARNED
     t0 = time.perf_counter()
-    fsm.mine_batch(graphs, sup, smax, mode, model=model, learn=True, train_steps=200, lr=3e-3)
+    fsm.mine_batch(tgraphs, [w["support"] for w in train_ws], smax, mode, model=model,
+                   learn=True, train_steps=200, lr=3e-3)
     t_train = time.perf_counter() - t0
-    print(f"[bench] warm-up batch with online training: {t_train:.3f} s", file=sys.stderr,
+    for g in tgraphs:
+        g.close()
+    print(f"[bench] online training on the disjoint batch (seeds 4000+g): {t_train:.3f} s",
+          file=sys.stderr, flush=True)
+    res, t_batch = timed(lambda: fsm.mine_batch(graphs, sup, smax, mode, model=model))
+    print(f"[bench] batched+learned (held-out batch): {t_batch:.3f} s", file=sys.stderr,
           flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = fsm.mine_batch(graphs, sup, smax, mode, model=model)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    print(f"[bench] batched+learned: {t_batch:.3f} s", file=sys.stderr, flush=True)
-    same = all(a.patterns == b.patterns for a, b in zip(plain, res))
+    same = all(a.patterns == b.patterns == c.patterns for a, b, c in zip(plain, bplain, res))
     emitted = sum(r.stats["levels"][n]["emitted"] for r in plain
                   for n in r.stats["levels"] if n >= 4)
+
+    def per_chunk(rs):
+        chunks = {}
+        for r in rs:
+            chunks.setdefault(r.stats["batch_chunk"], r)
+        return list(chunks.values())
+
     passes = lambda rs: sum(r.stats["levels"][n]["domain_passes"] for r in rs
                             for n in r.stats["levels"] if n >= 4)
-    chunks = {}
-    for r in res:
-        chunks.setdefault(r.stats["batch_chunk"], r)
     model.close()
     fsm.reset_tuning()
     for g in graphs:
         g.close()
     return {"workload": "batch256", "graphs": len(ws), "max_size": smax,
             "patterns": int(sum(len(r) for r in plain)), "embeddings_extended": emitted,
-            "plain_s": round(t_plain, 3), "batched_learned_s": round(t_batch, 3),
+            "plain_s": round(t_plain, 3), "batched_plain_sizing_s": round(t_bplain, 3),
+            "batched_learned_s": round(t_batch, 3),
             "speedup": round(t_plain / t_batch, 3),
+            "speedup_batching_alone": round(t_plain / t_bplain, 3),
+            "speedup_learned_over_batched": round(t_bplain / t_batch, 3),
             "plain_embeddings_per_s": round(emitted / t_plain, 1),
             "batched_learned_embeddings_per_s": round(emitted / t_batch, 1),
-            "chunks": len(chunks),
+            "chunks": len(per_chunk(res)),
             "domain_passes_plain": passes(plain),
-            "domain_passes_batched_learned": passes(chunks.values()),
-            "online_training_batch_s": round(t_train, 3),
+            "domain_passes_batched_plain_sizing": passes(per_chunk(bplain)),
+            "domain_passes_batched_learned": passes(per_chunk(res)),
+            "training": "online, on a disjoint 256-graph batch (seeds 4000+g), excluded",
+            "training_s": round(t_train, 3),
             "tuned": tuned, "tuning_s": round(t_tune, 1),
             "tuning_candidates_ms": [[c, t, round(ms, 1)] for c, t, ms in cands],
             "exact_match_plain": same}
+
+
+def host_cpu():
+    """Model name (lscpu) and usable cores of the host that runs the oracle."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"model": model, "cores_available": cores}
+
+
+def small_config_leg(fsm, synth, oracle_too=True):
+    """The 3,300-vertex ER workload (t = 100, sizes 2..4): GPU fsm_mine wall
+    time (median of 5 after a warm-up) and the single-thread oracle's
+    (median of 3), with the exact-match check."""
+    import torch
+    w = synth.workload("er3300")
+    args = (w["n"], w["src"], w["dst"], w["vertex_labels"])
+    t, smax = w["support"], w["max_size"]
+    with fsm.Graph(*args) as g:
+        fsm.mine(g, t, smax)
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fsm.mine(g, t, smax)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+    out = {"workload": "er3300", "support": t, "max_size": smax, "patterns": len(r),
+           "gpu_ms_median": round(1e3 * sorted(times)[2], 3)}
+    if oracle_too:
+        import oracle
+        ot = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            want = oracle.mine(*args, t, smax)
+            ot.append(time.perf_counter() - c0)
+        out["oracle_ms_median"] = round(1e3 * sorted(ot)[1], 3)
+        out["exact_match_oracle"] = r.patterns == want
+    print(f"[bench] er3300: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def cost_model_leg(fsm, synth, max_size=5):
@@ -276,23 +396,7 @@ def main():
     dom = max((n for n in levels if n >= 4), key=lambda n: levels[n]["join_ms"], default=None)
     roofline = None
     if dom is not None:
-        ms = sum(r.stats["levels"][dom]["join_ms"] for r in results) / len(results)
-        nbytes = levels[dom]["algorithmic_bytes"]
-        achieved = nbytes / (ms / 1e3) / 1e9 if ms > 0 else 0.0
-        prof = profiled_counters(dom, args.workload)
-        traffic = None
-        valu = None
-        if prof is not None:
-            traffic = prof.get("traffic_bytes_per_launch")
-            if prof.get("SQ_INSTS_VALU"):
-                rate = prof["SQ_INSTS_VALU"] / (ms / 1e3)
-                valu = {"wave_insts_per_s": round(rate, 1), "peak": VALU_PEAK_WAVE_INSTS,
-                        "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4)}
-        roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                    "traffic": traffic, "kernel": f"k_join_tiles<{dom}, false> (domain pass)",
-                    "kernel_ms": round(ms, 3), "algorithmic_bytes": nbytes,
-                    "valu": valu}
+        roofline = join_roofline(results, dom, args.workload)
 
     single = None if args.no_single else single_vertex_leg(fsm, g, t, smax, ref)
     sampled = None if args.no_sampling else sampling_leg(fsm, g, t, smax, ref)
@@ -301,17 +405,25 @@ def main():
 
     cpu = None
     exact = None
+    small = None
     if not args.no_cpu_baseline:
         import oracle
         c0 = time.perf_counter()
         want = oracle.mine(w["n"], w["src"], w["dst"], w["vertex_labels"], t, smax)
         cdt = time.perf_counter() - c0
         exact = [tuple(p) for p in ref.patterns] == [tuple(p) for p in want]
-        cpu = {"value": round(emitted / cdt, 1), "unit": "embeddings extended/s", "cores": 1,
+        host = host_cpu()
+        # The oracle decides each pattern's support by an existence search per
+        # (orbit, candidate vertex); it extends no embeddings, so its figure is
+        # the FSM wall time of the same workload, not a rate in the device's unit.
+        cpu = {"value": round(cdt, 3), "unit": "s FSM wall time (whole workload)", "cores": 1,
                "kind": "oracle",
                "sample": f"whole workload: the single-thread oracle mines {args.workload} "
-                         f"(t={t}, sizes 2..{smax}) in {cdt:.2f} s; rate = the device's "
-                         f"{emitted} join-level subgraphs / that time"}
+                         f"(t={t}, sizes 2..{smax}, {len(want)} patterns) once",
+               "host_cpu": host["model"], "host_cores_available": host["cores_available"],
+               "gpu_step_s": round(dt / args.steps, 3),
+               "gpu_over_oracle_speedup": round(cdt / (dt / args.steps), 2)}
+        small = small_config_leg(fsm, synth)
 
     out = {
         "metric": "embeddings extended/s",
@@ -333,6 +445,7 @@ def main():
                    "exact_match_oracle": exact},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "small_config": small,
         "batch": batch,
         "single_vertex": single,
         "sampling": sampled,

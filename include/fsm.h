@@ -136,6 +136,12 @@ typedef struct {
                                  size-3 subgraph containing its joining
                                  vertex (two-vertex) or 8 per G_f edge of it
                                  (single-vertex), at most the ST sample */
+    int64_t canonical_forms;  /* canonical-form computations of the level:
+                                 one per quick pattern and canonical pass
+                                 (the analogue of the isomorphism-tool calls
+                                 counted in Section 6.2; a miner without
+                                 index-based quick patterns makes one per
+                                 emitted subgraph) */
 } fsm_level_stats;
 
 typedef struct {
@@ -195,6 +201,14 @@ typedef struct {
                                  each vertex (a wedge to its centre, a
                                  triangle to its smallest vertex) are kept
                                  and joined.  0: off */
+    int32_t force_overflow;   /* 1: every quick-pattern and canonical-pattern
+                                 table starts at 2 slots (hash_capacity_min,
+                                 pattern_capacity_min and learned sizing are
+                                 ignored), so every level overflows and
+                                 reruns its passes with grown tables; the
+                                 results are identical (a test of the
+                                 overflow path) */
+    int32_t reserved2;
 } fsm_options;
 
 /* Allocation hooks used for all device memory of later calls (e.g. a
@@ -446,6 +460,35 @@ const char *fsm_last_error(void);
  * Returns FSM_OK, FSM_EINVAL for bad arguments or a disconnected graph. */
 int fsm_dissect(int32_t n, const int32_t *ids, uint32_t adj, uint32_t *l_mask,
                 int32_t *shared);
+
+/* Keep thresholds of the learned sampling proposal (FSM_SAMPLED |
+ * FSM_LEARNED), run on the host with the code the miner uses.  Not part of
+ * the paper's method: for work item r with predicted children
+ * c_r = expm1(max(0, pred[r])) the keep rate is min(1, lambda / max(c_r, 1)),
+ * lambda chosen so that the expected work sum(rate_r c_r) equals
+ * rate * sum(c_r) (the uniform rate's); a piece of item r is kept when its
+ * sampling hash is below thresholds[r] (2^64 - 1: everything).  The result
+ * depends only on the multiset of rows (sums run over sorted costs), each
+ * rate relative to `rate` is rounded to 2^-20, and with no predicted work
+ * (or rate >= 1) every threshold is 2^64 - 1.
+ *   pred        rows host floats: log1p of predicted children per item
+ *   rate        the uniform sampling rate, in (0, 1]
+ *   thresholds  receives rows keep thresholds
+ * Returns FSM_OK, FSM_EINVAL for NULL arrays, rows < 0 or a rate outside
+ * (0, 1]. */
+int fsm_proposal_thresholds(const float *pred, int64_t rows, double rate,
+                            uint64_t *thresholds);
+
+/* Graph id carried by a pattern key of a batched call (the canonical code in
+ * the low bits, the graph id from bit 52 for sizes whose code leaves room,
+ * graph 0 otherwise), checked against the call's graph count: the miner
+ * decodes keys read back from the device with this check and reports
+ * FSM_EDEVICE instead of indexing with a graph id that names no graph.
+ *   key     pattern-table key; size  pattern size 2..7; graphs  graphs of
+ *           the call (>= 1); graph  receives the id
+ * Returns FSM_OK, FSM_EINVAL for bad arguments, FSM_EDEVICE when the key
+ * names no graph of the call. */
+int fsm_key_graph(uint64_t key, int32_t size, int32_t graphs, int32_t *graph);
 
 #ifdef __cplusplus
 }

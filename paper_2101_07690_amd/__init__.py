@@ -57,7 +57,7 @@ class LevelStats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("join_ms", ctypes.c_double),
                 ("domain_passes", ctypes.c_int64), ("qp_capacity", ctypes.c_int64),
                 ("qp_predicted", ctypes.c_int64), ("rank_slices", ctypes.c_int64),
-                ("hash_bytes", ctypes.c_int64)]
+                ("hash_bytes", ctypes.c_int64), ("canonical_forms", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -98,7 +98,8 @@ class Options(ctypes.Structure):
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("record", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
                 ("pool_budget_mib", ctypes.c_int64), ("join_threshold", ctypes.c_int64),
-                ("match_threshold", ctypes.c_int64)]
+                ("match_threshold", ctypes.c_int64), ("force_overflow", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -174,6 +175,11 @@ def lib():
     L.fsm_dissect.argtypes = [ctypes.c_int32, i32p, ctypes.c_uint32,
                               ctypes.POINTER(ctypes.c_uint32), i32p]
     L.fsm_dissect.restype = ctypes.c_int
+    L.fsm_proposal_thresholds.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int64,
+                                          ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+    L.fsm_proposal_thresholds.restype = ctypes.c_int
+    L.fsm_key_graph.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, i32p]
+    L.fsm_key_graph.restype = ctypes.c_int
     f32p = ctypes.POINTER(ctypes.c_float)
     L.fsm_model_param_count.argtypes = [ctypes.c_int32]
     L.fsm_model_param_count.restype = ctypes.c_int64
@@ -358,7 +364,7 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
          hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
          record: bool = False, schedule: int = FSM_SCHEDULE_QUEUE,
          tiles_per_wave: int = 0, pool_budget_mib: int = 0, join_threshold: int = 0,
-         match_threshold: int = 0) -> Result:
+         match_threshold: int = 0, force_overflow: bool = False) -> Result:
     """Frequent patterns of sizes 2..max_size with MNI support >= support.
     ``model`` (a Model with FEATURES inputs) sizes the join tables when
     ``mode`` has FSM_LEARNED; ``record`` keeps the join work-item rows.
@@ -368,6 +374,7 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
     o = Options()
     o.join_threshold = int(join_threshold)
     o.match_threshold = int(match_threshold)
+    o.force_overflow = 1 if force_overflow else 0
     o.model = model.handle.value if model is not None else None
     o.record = 1 if record else 0
     o.schedule = int(schedule)
@@ -550,3 +557,22 @@ def dissect(ids, adj):
     sh = ctypes.c_int32()
     _check(lib().fsm_dissect(n, ap, ctypes.c_uint32(adj), ctypes.byref(lm), ctypes.byref(sh)))
     return int(lm.value), int(sh.value)
+
+
+def proposal_thresholds(pred, rate: float):
+    """Keep thresholds of the learned sampling proposal for per-item
+    predictions ``pred`` (log1p of predicted children), as the miner
+    computes them (fsm_proposal_thresholds)."""
+    p = np.ascontiguousarray(pred, dtype=np.float32).ravel()
+    out = np.zeros(max(p.size, 1), np.uint64)
+    _check(lib().fsm_proposal_thresholds(
+        p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size, float(rate),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return out[:p.size]
+
+
+def key_graph(key: int, size: int, graphs: int) -> int:
+    """Graph id a batched pattern key carries, checked (fsm_key_graph)."""
+    g = ctypes.c_int32()
+    _check(lib().fsm_key_graph(ctypes.c_uint64(key), int(size), int(graphs), ctypes.byref(g)))
+    return int(g.value)

@@ -418,4 +418,26 @@ int fsm_dissect(int32_t n, const int32_t* ids, uint32_t adj, uint32_t* l_mask, i
     });
 }
 
+int fsm_proposal_thresholds(const float* pred, int64_t rows, double rate, uint64_t* thresholds) {
+    return guarded([&] {
+        if (rows < 0 || (rows > 0 && (!pred || !thresholds)))
+            fail(FSM_EINVAL, "fsm_proposal_thresholds: NULL array or rows < 0");
+        if (!(rate > 0.0 && rate <= 1.0))
+            fail(FSM_EINVAL, "fsm_proposal_thresholds: rate must be in (0, 1]");
+        proposal_keep_thresholds(pred, rows, rate, thresholds);
+    });
+}
+
+int fsm_key_graph(uint64_t key, int32_t size, int32_t graphs, int32_t* graph) {
+    return guarded([&] {
+        if (!graph || size < 2 || size > FSM_MAX_SIZE || graphs < 1)
+            fail(FSM_EINVAL, "fsm_key_graph: bad arguments");
+        const int gi = checked_code_graph(key, size, graphs);
+        if (gi < 0)
+            fail(FSM_EDEVICE, "fsm_key_graph: key 0x%llx of size %d names no graph of %d",
+                 (unsigned long long)key, size, graphs);
+        *graph = gi;
+    });
+}
+
 }  // extern "C"

@@ -229,4 +229,12 @@ FSM_HD int code_graph(uint64_t code, int n) {
     return code_has_graph(n) ? (int)(code >> CODE_GRAPH_SHIFT) : 0;
 }
 
+// Graph id of a size-n pattern key, or -1 when it names no graph of a call
+// with `graphs` graphs.
+FSM_HD int checked_code_graph(uint64_t code, int n, int graphs) {
+    if (n < 2 || n > MAXN) return -1;
+    const int gi = code_graph(code, n);
+    return gi < graphs ? gi : -1;
+}
+
 }  // namespace fsm

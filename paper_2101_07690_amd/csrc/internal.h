@@ -153,4 +153,5 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
 void set_tuning(int64_t chunk_vertices, int32_t tiles_per_wave);
 void tune_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
                 int32_t max_size, fsm_tuning* out);
+void proposal_keep_thresholds(const float* pred, int64_t rows, double rate, uint64_t* thr);
 }  // namespace fsm

@@ -58,7 +58,8 @@ constexpr uint64_t FREQ = 1ull << 62;
 constexpr uint64_t REGION_MASK = (1ull << 41) - 1;
 constexpr int JOIN_CHUNK = 4;   // work items fetched per queue access
 
-enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, ERR_MISSING = 8, ERR_FILL = 16, ERR_BATCH = 32 };
+enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, ERR_MISSING = 8, ERR_FILL = 16, ERR_BATCH = 32,
+                  ERR_GRAPH = 64 };
 enum { MODE_DOMAIN = 0, MODE_COUNT = 1, MODE_FILL = 2 };
 enum { PIECE_KC = 0, PIECE_KL = 1, PIECE_TR = 2 };   // k-centre wedge, k-leaf wedge, triangle
 
@@ -2276,6 +2277,7 @@ struct CanonArgs {
     uint32_t* flags;
     int n;
     uint64_t slots;
+    uint64_t ngraphs;   // graphs of the call: every packed graph id is below it
 };
 
 // One thread per QP: canonical form (the one isomorphism computation of
@@ -2286,6 +2288,10 @@ __global__ void k_qp_canon(CanonArgs a) {
         if (a.q.kv[2 * s] == EMPTY_KEY) continue;
         const uint64_t L = a.q.lab[s];
         const uint64_t gid = L >> 48;
+        if (gid >= a.ngraphs) {   // a corrupted key layout, never a valid graph
+            atomicOr(a.flags, ERR_GRAPH);
+            continue;
+        }
         const Canon cn = canonicalize(a.n, L, a.q.adj[s]);
         if (gid && !code_has_graph(a.n)) {
             atomicOr(a.flags, ERR_BATCH);
@@ -2408,7 +2414,7 @@ __global__ void k_pattern_counts(QPTab q, uint64_t slots, const unsigned long lo
 // cand[s*n+o] = 1 for the orbit representatives o of candidate pattern slots.
 __global__ void k_candidate_flags(CodeTab c, uint64_t slots, int n,
                                   const unsigned long long* pcnt, const int64_t* tg,
-                                  int64_t* cand) {
+                                  int ngraphs, int64_t* cand, uint32_t* flags) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < slots * n;
          x += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t s = x / n;
@@ -2417,7 +2423,9 @@ __global__ void k_candidate_flags(CodeTab c, uint64_t slots, int n,
         const uint64_t key = c.kv[2 * s];
         if (key != EMPTY_KEY) {
             const uint64_t info = c.info[s];
-            if ((info & VALID) && (int)((info >> (3 * p)) & 7u) == p) {
+            const int gi = code_graph(key, n);
+            if (gi >= ngraphs) atomicOr(flags, ERR_GRAPH);
+            if ((info & VALID) && gi < ngraphs && (int)((info >> (3 * p)) & 7u) == p) {
                 int smallest = n;   // smallest orbit size
                 for (int r = 0; r < n; ++r) {
                     if ((int)((info >> (3 * r)) & 7u) != r) continue;
@@ -2425,8 +2433,7 @@ __global__ void k_candidate_flags(CodeTab c, uint64_t slots, int n,
                     for (int q = 0; q < n; ++q) size += (int)((info >> (3 * q)) & 7u) == r;
                     smallest = min(smallest, size);
                 }
-                if (pcnt[s] * (unsigned long long)smallest >=
-                    (unsigned long long)tg[code_graph(key, n)])
+                if (pcnt[s] * (unsigned long long)smallest >= (unsigned long long)tg[gi])
                     f = 1;
             }
         }
@@ -2493,14 +2500,19 @@ __global__ void k_qp_rehash(QPTab from, uint64_t slots, QPTab to, uint32_t* flag
 
 // FREQ bit on every QP whose pattern reached its graph's threshold
 __global__ void k_mark_frequent(QPTab q, uint64_t slots, const uint64_t* ckv, const int64_t* sup,
-                                const int64_t* tg, int n) {
+                                const int64_t* tg, int ngraphs, int n, uint32_t* flags) {
     for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
          s += (uint64_t)gridDim.x * blockDim.x) {
         if (q.kv[2 * s] == EMPTY_KEY) continue;
         uint64_t v = q.kv[2 * s + 1];
         if (!(v & VALID)) continue;
         const int32_t p = q.pat[s];
-        if (sup[p] >= tg[code_graph(ckv[2 * p], n)]) q.kv[2 * s + 1] = v | FREQ;
+        const int gi = code_graph(ckv[2 * p], n);
+        if (gi >= ngraphs) {
+            atomicOr(flags, ERR_GRAPH);
+            continue;
+        }
+        if (sup[p] >= tg[gi]) q.kv[2 * s + 1] = v | FREQ;
     }
 }
 
@@ -2817,6 +2829,39 @@ uint64_t pow2_at_least(uint64_t x) {
     return p;
 }
 
+// Two HIP events timing device work on one stream; inert (no events, 0 ms)
+// when timing is off, as in calls that must not create runtime objects.
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    Timer(bool on, hipStream_t st) : s(st) {
+        if (!on) return;
+        FSM_HIP(hipEventCreate(&a));
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = nullptr;
+            fail(FSM_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    Timer(const Timer&) = delete;
+    Timer& operator=(const Timer&) = delete;
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start() {
+        if (a) FSM_HIP(hipEventRecord(a, s));
+    }
+    float stop() {
+        if (!a) return 0.f;
+        FSM_HIP(hipEventRecord(b, s));
+        FSM_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        FSM_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+};
+
 struct Miner {
     GraphView gv;
     const GraphView* g = &gv;
@@ -2867,6 +2912,7 @@ struct Miner {
     DBuf<uint32_t> flags;
     uint32_t W = 1;
     unsigned grid_persistent = 1024;
+    bool timing = true;          // per-level HIP-event timings (off: 0 ms)
     Level lv[FSM_MAX_SIZE + 1];
     std::vector<fsm_result*> res;         // one per graph
 
@@ -2886,8 +2932,34 @@ struct Miner {
     void item_rows(const Level& P, int n, ItemRows& IR);
 
     uint64_t qcap0() const {
+        if (opt.force_overflow) return 2;
         uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 14);
         return pow2_at_least(c);
+    }
+
+    // Graph of a pattern key decoded on the host, checked against the
+    // call's graphs: a key-layout mistake is reported, never used to index.
+    size_t graph_of(uint64_t code, int n) const {
+        const int32_t gi = checked_code_graph(code, n, g->ngraphs);
+        if (gi < 0)
+            fail(FSM_EDEVICE, "pattern key 0x%llx of size %d names no graph of the call (%d graphs)",
+                 (unsigned long long)code, n, g->ngraphs);
+        return (size_t)gi;
+    }
+
+    // Next QP table size after an overflow: 16 times larger, or less when
+    // that table would not fit the free device memory (36 bytes per slot:
+    // key, value, ordered adjacency and labels, pattern slot).
+    uint64_t grown_qp_capacity(uint64_t qcap, int n) const {
+        size_t fr = 0, tot = 0;
+        FSM_HIP(hipMemGetInfo(&fr, &tot));
+        const uint64_t room = (uint64_t)fr + qcap * 36ull;   // the old table is freed first
+        uint64_t next = qcap * 16;
+        while (next > qcap * 2 && next * 36ull > room / 2) next /= 2;
+        if (fsm_trace())
+            std::fprintf(stderr, "[fsm] size %d: QP table %llu -> %llu slots\n", n,
+                         (unsigned long long)qcap, (unsigned long long)next);
+        return next;
     }
 
     Rec rec(Level& L) {
@@ -2929,16 +3001,24 @@ struct Miner {
     // table.  launch(R, pass) runs the level's domain kernel.
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
-        uint64_t qcap = L.tab.qcap ? L.tab.qcap : std::max(qcap0(), qhint[L.n]);
+        uint64_t qcap = L.tab.qcap ? L.tab.qcap
+                                   : (opt.force_overflow ? qcap0() : std::max(qcap0(), qhint[L.n]));
         DBuf<unsigned long long> qcnt;
         const int64_t ranks = (int64_t)W * 32;
         uint32_t w0 = W;
+        // child keys of a later join carry this level's QP slots in 29 bits;
+        // the last level's slots go into no key (its limits are the 32-bit
+        // QP counter and the int32 pattern slots)
+        const bool parent_level = (opt.mode & FSM_SINGLE) ? L.n + 1 <= opt.max_size
+                                                          : L.n + 2 <= opt.max_size;
+        const uint64_t qcap_max = parent_level ? (1ull << 29) : (1ull << 32);
         for (int attempt = 0;; ++attempt) {
             L.st.domain_passes = attempt + 1;
             L.st.qp_capacity = (int64_t)qcap;
-            // child keys carry the parent's QP slot in 29 bits
-            if (qcap > (1ull << 29))
-                fail(FSM_EOVERFLOW, "more than 2^28 quick patterns at size %d", L.n);
+            if (qcap > qcap_max)
+                fail(FSM_EOVERFLOW, "more than %llu quick patterns at size %d%s",
+                     (unsigned long long)(qcap_max / 2), L.n,
+                     parent_level ? " (a later join keys children by 29-bit parent slots)" : "");
             if (L.tab.qcap != qcap) L.tab.alloc(qcap, 1);
             L.tab.reset_qp();
             w0 = slice_words(qcap, L.n);
@@ -2963,8 +3043,9 @@ struct Miner {
             if (f & (ERR_MISSING | ERR_FILL))
                 fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", L.n, f);
             if (!(f & OVF_QP)) break;
-            if (attempt >= 8) fail(FSM_EOVERFLOW, "QP table kept overflowing at size %d", L.n);
-            qcap *= 16;
+            if (attempt >= (opt.force_overflow ? 16 : 8))
+                fail(FSM_EOVERFLOW, "QP table kept overflowing at size %d", L.n);
+            qcap = grown_qp_capacity(qcap, L.n);
         }
         std::vector<unsigned long long> cnt;
         to_host(cnt, counters.p, 4);
@@ -2974,8 +3055,11 @@ struct Miner {
         const unsigned nqp = scalar_to_host(L.tab.qcount.p);
         L.st.quick_patterns = nqp;
         // canonical forms: pattern table sized for every QP being its own pattern
-        uint64_t ccap = pow2_at_least(std::max<uint64_t>(
-            2ull * nqp + 16, (uint64_t)std::max<int64_t>(opt.pattern_capacity_min, 16)));
+        uint64_t ccap = opt.force_overflow
+                            ? 2
+                            : pow2_at_least(std::max<uint64_t>(
+                                  2ull * nqp + 16,
+                                  (uint64_t)std::max<int64_t>(opt.pattern_capacity_min, 16)));
         for (int attempt = 0;; ++attempt) {
             L.tab.alloc_codes(ccap);
             L.tab.reset_codes();
@@ -2984,14 +3068,20 @@ struct Miner {
                           L.tab.qcount.p},
                          {L.tab.ckv.p, L.tab.ccap - 1, L.tab.cinfo.p, L.tab.csup.p,
                           L.tab.ccount.p},
-                         flags.p, L.n, L.tab.qcap};
+                         flags.p, L.n, L.tab.qcap, (uint64_t)g->ngraphs};
             k_qp_canon<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(ca);
             FSM_LAUNCH_CHECK();
+            // one canonical form per quick pattern (Section 4.4: one
+            // isomorphism computation per quick-pattern group)
+            L.st.canonical_forms += nqp;
             const uint32_t cf = scalar_to_host(flags.p);
+            if (cf & ERR_GRAPH)
+                fail(FSM_EDEVICE, "a quick pattern at size %d names no graph of the call", L.n);
             if (cf & ERR_BATCH)
                 fail(FSM_EUNSUPPORTED, "batches of several graphs support sizes up to 6");
             if (!(cf & OVF_CODE)) break;
-            if (attempt >= 4) fail(FSM_EOVERFLOW, "pattern table overflow at size %d", L.n);
+            if (attempt >= (opt.force_overflow ? 16 : 4))
+                fail(FSM_EOVERFLOW, "pattern table overflow at size %d", L.n);
             ccap *= 4;
         }
         const unsigned npat = scalar_to_host(L.tab.ccount.p);
@@ -3037,9 +3127,12 @@ struct Miner {
             const uint64_t items = ccap * (uint64_t)L.n;
             cand.alloc(items);
             poidx.alloc(items);
-            k_candidate_flags<<<grid_for((int64_t)items, TPB), TPB, 0, st>>>(ct, ccap, L.n, pcnt.p,
-                                                                            dtg.p, cand.p);
+            flags.zero();
+            k_candidate_flags<<<grid_for((int64_t)items, TPB), TPB, 0, st>>>(
+                ct, ccap, L.n, pcnt.p, dtg.p, g->ngraphs, cand.p, flags.p);
             FSM_LAUNCH_CHECK();
+            if (scalar_to_host(flags.p) & ERR_GRAPH)
+                fail(FSM_EDEVICE, "a pattern at size %d names no graph of the call", L.n);
             npo = scan_exclusive(cand.p, poidx.p, (int64_t)items);
             if (npo >= (int64_t)INT32_MAX)
                 fail(FSM_EUNSUPPORTED, "more than 2^31 candidate orbit domains at size %d", L.n);
@@ -3125,16 +3218,19 @@ struct Miner {
         MniArgs m{ct, {ppool.p, lrank.p, W, 0}, L.n, L.tab.ccap, okey.p, osup.p, on.p, npat};
         k_mni<<<grid_for((int64_t)L.tab.ccap, TPB), TPB, 0, st>>>(m, ocnt.p);
         FSM_LAUNCH_CHECK();
+        flags.zero();
         k_mark_frequent<<<grid_for((int64_t)L.tab.qcap, TPB), TPB, 0, st>>>(
-            q, L.tab.qcap, L.tab.ckv.p, L.tab.csup.p, dtg.p, L.n);
+            q, L.tab.qcap, L.tab.ckv.p, L.tab.csup.p, dtg.p, g->ngraphs, L.n, flags.p);
         FSM_LAUNCH_CHECK();
         std::vector<uint64_t> hk;
         std::vector<int64_t> hs;
         to_host(hk, okey.p, npat);
         to_host(hs, osup.p, npat);
+        if (scalar_to_host(flags.p) & ERR_GRAPH)
+            fail(FSM_EDEVICE, "a pattern at size %d names no graph of the call", L.n);
         L.freq.clear();
         for (unsigned i = 0; i < npat; ++i)
-            if (hs[i] >= tg[(size_t)code_graph(hk[i], L.n)]) L.freq.emplace_back(hk[i], hs[i]);
+            if (hs[i] >= tg[graph_of(hk[i], L.n)]) L.freq.emplace_back(hk[i], hs[i]);
         std::sort(L.freq.begin(), L.freq.end());
         L.st.frequent = (int64_t)L.freq.size();
     }
@@ -3196,7 +3292,7 @@ void Miner::build_gf() {
     std::vector<uint8_t> f2((size_t)g->ngraphs * F * F, 0);
     for (auto& kv : lv[2].freq) {
         const int a = code_label(kv.first, 2, 0), b = code_label(kv.first, 2, 1);
-        uint8_t* t = f2.data() + (size_t)code_graph(kv.first, 2) * F * F;
+        uint8_t* t = f2.data() + graph_of(kv.first, 2) * F * F;
         t[(size_t)a * F + b] = t[(size_t)b * F + a] = 1;
     }
     DBuf<uint8_t> df2(f2.size());
@@ -3340,7 +3436,7 @@ void Miner::level3() {
     std::vector<uint8_t> t2(2 * FF * (size_t)g->ngraphs, 0);
     for (auto& kv : L.freq) {
         const uint64_t code = kv.first;
-        uint8_t* t = t2.data() + 2 * FF * (size_t)code_graph(code, 3);
+        uint8_t* t = t2.data() + 2 * FF * graph_of(code, 3);
         int l0 = code_label(code, 3, 0), l1 = code_label(code, 3, 1), l2 = code_label(code, 3, 2);
         const uint32_t seq = (uint32_t)(code & 7u);   // bits: (0,1) (0,2) (1,2)
         int ls[3] = {l0, l1, l2};
@@ -3497,31 +3593,17 @@ void Miner::proposal_thresholds(const ItemRows& IR, const float* y, int64_t nite
     to_host(hy, y, (size_t)(IR.rows * MODEL_OUT));
     to_host(hi, IR.item.p, (size_t)IR.rows);
     const size_t R = (size_t)IR.rows;
-    std::vector<double> c(R), wgt(R);
-    double total = 0.0;
-    for (size_t r = 0; r < R; ++r) {
-        c[r] = std::expm1(std::max(0.0, (double)hy[2 * r]));
-        wgt[r] = 1.0 / std::max(c[r], 1.0);
-        total += c[r];
-    }
-    const double budget = opt.sampling_rate * total;
-    auto work = [&](double lam) {
-        double s = 0.0;
-        for (size_t r = 0; r < R; ++r) s += std::min(1.0, lam * wgt[r]) * c[r];
-        return s;
-    };
-    double lo = 0.0, hi_l = 1.0;
-    while (work(hi_l) < budget && hi_l < 1e30) hi_l *= 2.0;
-    for (int it = 0; it < 100; ++it) {
-        const double mid = 0.5 * (lo + hi_l);
-        if (work(mid) < budget) lo = mid; else hi_l = mid;
-    }
-    const double lam = hi_l;
+    std::vector<float> pred(R);
+    for (size_t r = 0; r < R; ++r) pred[r] = hy[2 * r];
+    std::vector<uint64_t> rt(R);
+    proposal_keep_thresholds(pred.data(), (int64_t)R, opt.sampling_rate, rt.data());
     const uint64_t uni = (uint64_t)std::ldexp(opt.sampling_rate, 64);
     std::vector<uint64_t> h((size_t)nitems, uni);
     for (size_t r = 0; r < R; ++r) {
-        const double rate = std::min(1.0, lam * wgt[r]);
-        h[(size_t)hi[r]] = rate >= 1.0 ? ~0ull : (uint64_t)std::ldexp(rate, 64);
+        if (hi[r] < 0 || (int64_t)hi[r] >= nitems)
+            fail(FSM_EDEVICE, "work-item row %zu names item %d of %lld", r, hi[r],
+                 (long long)nitems);
+        h[(size_t)hi[r]] = rt[r];
     }
     thr.alloc((size_t)nitems);
     to_device(thr.p, h.data(), h.size());
@@ -3737,10 +3819,8 @@ void Miner::join(int n) {
     // sampling, vertex-induced and candidate-bitmap paths
     const bool extra = (opt.mode & (FSM_SAMPLED | FSM_INDUCED)) || ithr.p || smp.kthr ||
                        smp.ethr || smp.mthr;
-    hipEvent_t j0, j1;
-    FSM_HIP(hipEventCreate(&j0));
-    FSM_HIP(hipEventCreate(&j1));
-    try {
+    {
+        Timer jt(timing, st);
         float join_total = 0.f;
         domain_level(L, [&](Rec R, int pass) {
             // recording: pass 0 sees every child and inserts every QP
@@ -3750,7 +3830,7 @@ void Miner::join(int n) {
                 R.item_qps = iqp.p;
             }
             if (pass == 0) join_total = 0.f;   // a new attempt
-            FSM_HIP(hipEventRecord(j0, st));
+            jt.start();
             if (G.ntiles > 0) {
                 TileArgs t = tile_args(R);
                 t.item_children = pass == 0 ? ich.p : nullptr;
@@ -3770,20 +3850,10 @@ void Miner::join(int n) {
 #undef FSM_TILES_CASE
                 FSM_LAUNCH_CHECK();
             }
-            FSM_HIP(hipEventRecord(j1, st));
-            float ms = 0;
-            FSM_HIP(hipEventSynchronize(j1));
-            FSM_HIP(hipEventElapsedTime(&ms, j0, j1));
-            join_total += ms;
+            join_total += jt.stop();
         });
         L.st.join_ms = join_total;
-    } catch (...) {
-        (void)hipEventDestroy(j0);
-        (void)hipEventDestroy(j1);
-        throw;
     }
-    (void)hipEventDestroy(j0);
-    (void)hipEventDestroy(j1);
     if (pred_raw > 0.0 && L.st.quick_patterns > 0)
         model->calib[n] = (double)L.st.quick_patterns / pred_raw;
     if (ich.p) {
@@ -3892,14 +3962,12 @@ void Miner::join_single(int n) {
         t.smp = smp;
         return t;
     };
-    hipEvent_t j0, j1;
-    FSM_HIP(hipEventCreate(&j0));
-    FSM_HIP(hipEventCreate(&j1));
-    try {
+    {
+        Timer jt(timing, st);
         float join_total = 0.f;
         domain_level(L, [&](Rec R, int pass) {
             if (pass == 0) join_total = 0.f;
-            FSM_HIP(hipEventRecord(j0, st));
+            jt.start();
             if (G.ntiles > 0) {
                 const SingleTileArgs t = tile_args(R);
                 switch (n) {
@@ -3912,20 +3980,10 @@ void Miner::join_single(int n) {
                 }
                 FSM_LAUNCH_CHECK();
             }
-            FSM_HIP(hipEventRecord(j1, st));
-            float ms = 0;
-            FSM_HIP(hipEventSynchronize(j1));
-            FSM_HIP(hipEventElapsedTime(&ms, j0, j1));
-            join_total += ms;
+            join_total += jt.stop();
         });
         L.st.join_ms = join_total;
-    } catch (...) {
-        (void)hipEventDestroy(j0);
-        (void)hipEventDestroy(j1);
-        throw;
     }
-    (void)hipEventDestroy(j0);
-    (void)hipEventDestroy(j1);
     if (n + 1 <= opt.max_size) {
         materialize(L, nwork, [&](int mode, int64_t* counts, const int64_t* offsets, int32_t* out,
                                   int64_t rows) {
@@ -3938,6 +3996,8 @@ void Miner::emit_results() {
     if (opt.record) {
         const size_t rows = rl.size();
         for (size_t r = 0; r < rows; ++r) {
+            if (rg[r] < 0 || rg[r] >= g->ngraphs)
+                fail(FSM_EDEVICE, "training row %zu names graph %d of %d", r, rg[r], g->ngraphs);
             fsm_result* out = res[(size_t)rg[r]];
             out->tx.insert(out->tx.end(), rx.begin() + (long)(r * FSM_FEATURES),
                            rx.begin() + (long)((r + 1) * FSM_FEATURES));
@@ -3957,7 +4017,7 @@ void Miner::emit_results() {
             const uint32_t seq = code_seq(kv.first, n);
             for (int k = 0; k < npairs; ++k)
                 if ((seq >> (npairs - 1 - k)) & 1u) c.adj |= 1u << k;
-            fsm_result* r = res[(size_t)code_graph(kv.first, n)];
+            fsm_result* r = res[graph_of(kv.first, n)];
             r->size.push_back(n);
             r->code.push_back(c);
             r->support.push_back(kv.second);
@@ -4035,17 +4095,11 @@ void Miner::run() {
     counters.alloc(4);
     flags.alloc(1);
 
-    hipEvent_t e0, e1;
-    FSM_HIP(hipEventCreate(&e0));
-    FSM_HIP(hipEventCreate(&e1));
+    Timer lt(timing, st);
     auto timed = [&](int n, auto&& body) {
-        FSM_HIP(hipEventRecord(e0, st));
+        lt.start();
         body();
-        FSM_HIP(hipEventRecord(e1, st));
-        FSM_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        FSM_HIP(hipEventElapsedTime(&ms, e0, e1));
-        lv[n].st.kernel_ms = ms;
+        lv[n].st.kernel_ms = lt.stop();
     };
     // level-2 embeddings: the edges of G_f (u < w)
     auto materialize_edges = [&] {
@@ -4059,7 +4113,7 @@ void Miner::run() {
             FSM_LAUNCH_CHECK();
         });
     };
-    try {
+    {
         timed(2, [&] { level2(); });
         build_gf();
         if (opt.mode & FSM_SINGLE) {
@@ -4107,13 +4161,7 @@ void Miner::run() {
                 if (n + 2 > opt.max_size) lv[n].tab = Tables();
             }
         }
-    } catch (...) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        throw;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     for (fsm_result* r : res)
         for (int n = 2; n <= opt.max_size; ++n) r->stats.level[n] = lv[n].st;
     emit_results();
@@ -4123,6 +4171,47 @@ void Miner::run() {
 }
 
 }  // namespace
+
+// Keep thresholds of the sampling proposal from per-row predictions
+// (log1p of predicted children).  Every sum runs over the predicted costs
+// in ascending order, so the result depends on the multiset of rows and not
+// on their order (work-item rows come out in QP-slot order, which CAS races
+// decide); a row's rate, relative to the uniform rate, is rounded to 2^-20
+// before it becomes a threshold, so an item whose rate equals the uniform
+// one gets exactly the uniform threshold.  With no predicted work every row
+// keeps everything.
+void proposal_keep_thresholds(const float* pred, int64_t rows, double rate, uint64_t* thr) {
+    const size_t R = (size_t)std::max<int64_t>(rows, 0);
+    std::vector<double> c(R);
+    for (size_t r = 0; r < R; ++r) c[r] = std::expm1(std::max(0.0, (double)pred[r]));
+    std::vector<double> sc(c);
+    std::sort(sc.begin(), sc.end());
+    double total = 0.0;
+    for (double v : sc) total += v;
+    const double budget = rate * total;
+    if (!(rate < 1.0) || !(budget > 0.0)) {
+        for (size_t r = 0; r < R; ++r) thr[r] = ~0ull;
+        return;
+    }
+    auto work = [&](double lam) {
+        double s = 0.0;
+        for (double v : sc) s += std::min(1.0, lam / std::max(v, 1.0)) * v;
+        return s;
+    };
+    double lo = 0.0, hi = 1.0;
+    while (work(hi) < budget && hi < 1e30) hi *= 2.0;
+    for (int it = 0; it < 100; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (work(mid) < budget) lo = mid; else hi = mid;
+    }
+    const double lam = hi;
+    for (size_t r = 0; r < R; ++r) {
+        const double rel = std::min(1.0, lam / std::max(c[r], 1.0)) / rate;
+        const double q = std::nearbyint(rel * 1048576.0) / 1048576.0;   // 2^-20 grid
+        const double keep = rate * q;
+        thr[r] = keep >= 1.0 ? ~0ull : (uint64_t)std::ldexp(keep, 64);
+    }
+}
 
 void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r) {
     Miner m;

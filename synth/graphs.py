@@ -173,8 +173,9 @@ def batch_workload(count: int = 256, seed: int = 3000):
 
     Graph g has ``n_g = round(exp(U[ln 500, ln 20000]))`` vertices, average
     degree ``U[4, 12]``, Chung-Lu exponent 2.1 capped at 64, 10 uniform labels,
-    and support ``ceil(0.02 n_g)``; seeds ``3000+g`` (graph), ``13000+g``
-    (labels).
+    and support ``ceil(0.02 n_g)``; seeds ``seed+g`` (graph), ``seed+10000+g``
+    (labels), with the sizes drawn from ``seed`` (3000: the benchmark batch;
+    another seed gives a disjoint batch of the same shape).
     """
     rng = np.random.default_rng(seed)
     ns = np.rint(np.exp(rng.uniform(math.log(500), math.log(20000), count)))
@@ -183,8 +184,8 @@ def batch_workload(count: int = 256, seed: int = 3000):
     for g in range(count):
         n = int(ns[g])
         m = int(round(n * ds[g] / 2))
-        src, dst = chung_lu_graph(n, m, 2.1, 64.0, 3000 + g)
-        labels = labels_uniform(n, 10, 13000 + g)
+        src, dst = chung_lu_graph(n, m, 2.1, 64.0, seed + g)
+        labels = labels_uniform(n, 10, seed + 10000 + g)
         out.append(dict(name=f"batch{g}", n=n, m=m, src=src, dst=dst,
                         vertex_labels=labels, support=int(math.ceil(0.02 * n)),
                         max_size=5))

@@ -16,20 +16,25 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-# (file stem, workload, support, max size)
+# (file stem, workload, support, max size, workload overrides)
 CASES = [
-    ("er3300_t10_s6", "er3300", 10, 6),
-    ("cl100k_t10000_s5", "cl100k", 10_000, 5),
+    ("er3300_t10_s6", "er3300", 10, 6, {}),
+    ("cl100k_t10000_s5", "cl100k", 10_000, 5, {}),
+    # the 1M-vertex, 37-label workload's generator at 1/10 scale (same
+    # seeds, exponent, degree cap and label law; t = 2% of the vertices as
+    # there), mined to its stated size 6
+    ("cl1m_tenth_t2000_s6", "cl1m", 2_000, 6, {"n": 100_000, "m": 1_200_000}),
 ]
 
 
-def write(stem, name, support, max_size):
-    w = synth.workload(name)
+def write(stem, name, support, max_size, override):
+    w = synth.workload(name, **override)
     t0 = time.time()
     pats = oracle.mine(w["n"], w["src"], w["dst"], w["vertex_labels"], support, max_size)
     dt = time.time() - t0
     out = {
         "workload": name,
+        "overrides": override,
         "support": support,
         "max_size": max_size,
         "graph_sha256": synth.graph_sha256(w["src"], w["dst"], w["vertex_labels"]),

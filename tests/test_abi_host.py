@@ -349,3 +349,60 @@ def test_theorem1_seven_vertex_sample_splits():
     rng = np.random.default_rng(77)
     got = sum(_check_split(7, int(adj), L) for adj in rng.integers(0, 1 << 21, 20000))
     assert got > 15000
+
+
+def test_proposal_thresholds_ignore_row_order():
+    """Work-item rows come out in QP-slot order, which the device's CAS
+    races decide; the thresholds must be a function of each row's prediction
+    and the multiset of all rows."""
+    rng = np.random.default_rng(11)
+    pred = np.log1p(rng.lognormal(3.0, 2.0, 5000)).astype(np.float32)
+    pred[::7] = 0.0                     # items predicted empty
+    for rate in (0.05, 0.1, 0.3):
+        base = fsm.proposal_thresholds(pred, rate)
+        for s in range(4):
+            perm = np.random.default_rng(s).permutation(pred.size)
+            got = fsm.proposal_thresholds(pred[perm], rate)
+            assert np.array_equal(got, base[perm])
+
+
+def test_proposal_thresholds_special_cases():
+    """Equal predictions give every item the uniform rate's threshold
+    exactly (int(rate * 2^64)); no predicted work, or rate 1, keeps
+    everything; the expected work equals the uniform rate's."""
+    full = np.uint64((1 << 64) - 1)
+    for rate in (0.1, 0.25, 0.5):
+        uni = np.uint64(int(np.ldexp(rate, 64)))
+        for c in (0.3, 1.0, 7.5, 1e4):
+            thr = fsm.proposal_thresholds(np.full(333, np.log1p(c), np.float32), rate)
+            assert (thr == uni).all()
+        assert (fsm.proposal_thresholds(np.zeros(50, np.float32), rate) == full).all()
+    assert (fsm.proposal_thresholds(np.full(9, 3.0, np.float32), 1.0) == full).all()
+    rng = np.random.default_rng(5)
+    pred = np.log1p(rng.lognormal(2.0, 1.5, 2000)).astype(np.float32)
+    c = np.expm1(pred.astype(np.float64))
+    thr = fsm.proposal_thresholds(pred, 0.1).astype(np.float64)
+    keep = np.minimum(1.0, thr / 2.0 ** 64)
+    assert abs((keep * c).sum() / (0.1 * c.sum()) - 1.0) < 1e-4
+    # cheap items are enumerated whole, heavy ones thinned
+    assert keep[c.argmin()] == 1.0 and keep[c.argmax()] < 0.1
+    with pytest.raises(fsm.FsmError):
+        fsm.proposal_thresholds(pred, 0.0)
+
+
+def test_key_graph_rejects_forged_keys():
+    """The host decodes graph ids of pattern keys read back from the device
+    with a bounds check: a key naming a graph outside the call is an error,
+    not an index."""
+    code5 = (3 << 24) | 0b1011   # any size-5 code (labels, pair bits)
+    assert fsm.key_graph((2 << 52) | code5, 5, 3) == 2
+    assert fsm.key_graph(code5, 5, 1) == 0
+    for g in (3, 4095):
+        with pytest.raises(fsm.FsmError) as e:
+            fsm.key_graph((g << 52) | code5, 5, 3)
+        assert e.value.code == -3
+    # size-7 codes take 63 bits and carry no graph id
+    assert fsm.key_graph((1 << 62) | 5, 7, 1) == 0
+    with pytest.raises(fsm.FsmError) as e:
+        fsm.key_graph(code5, 8, 3)
+    assert e.value.code == -1

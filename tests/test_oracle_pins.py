@@ -260,3 +260,47 @@ def test_induced_pattern_support_agrees_with_mine():
     n = len(lab)
     for size, labs, adj, sup in oracle.mine(n, s, d, lab, 1, 4, induced=True):
         assert oracle.pattern_support(n, s, d, lab, list(labs), adj, induced=True) == sup
+
+
+def _dirty_copy(src, dst, n, seed):
+    """The same simple graph written with every pair repeated (reversed, and
+    half of them twice in order), self-loops added, in shuffled order."""
+    rng = np.random.default_rng(seed)
+    ds, dd = [int(a) for a in src], [int(b) for b in dst]
+    for a, b in zip(src, dst):
+        ds.append(int(b)); dd.append(int(a))
+        if rng.random() < 0.5:
+            ds.append(int(a)); dd.append(int(b))
+    for v in rng.choice(n, size=3):
+        ds.append(int(v)); dd.append(int(v))
+    perm = rng.permutation(len(ds))
+    return np.array(ds, np.int32)[perm], np.array(dd, np.int32)[perm]
+
+
+def test_self_loops_and_repeated_pairs_are_dropped():
+    """The oracle's graph normalisation (simple graph: loops dropped,
+    repeated and reversed pairs merged) pinned against the clean input and
+    against the brute force, which normalises with code of its own."""
+    for seed in range(8):
+        s, t, lab = synth.tiny_graph(9100 + seed, 8, 11, 2)
+        n = len(lab)
+        ds, dt = _dirty_copy(s, t, n, seed)
+        for sup in (1, 2):
+            clean = oracle.mine(n, s, t, lab, sup, 5)
+            dirty = oracle.mine(n, ds, dt, lab, sup, 5)
+            assert dirty == clean
+            assert dirty == brute.mine(n, ds, dt, lab, sup, 5)
+        assert oracle.count_connected(n, ds, dt, 4) == oracle.count_connected(n, s, t, 4)
+
+
+def test_repeated_pairs_do_not_inflate_a_star():
+    """Star K_{1,3} written with every edge four times and a loop at the
+    centre: the edge pattern has support 4 (d + 1, one merged orbit), the
+    wedge 1, the 3-star 1 -- as for the clean star."""
+    s = [0, 1, 0, 2, 0, 3] * 2 + [0]
+    t = [1, 0, 2, 0, 3, 0] * 2 + [0]
+    got = oracle.mine(4, s, t, [0, 0, 0, 0], 1, 4)
+    sup = {(p[0], p[2]): p[3] for p in got}
+    assert sup[(2, 1)] == 4
+    assert [p[3] for p in got if p[0] == 3] == [1]
+    assert [p[3] for p in got if p[0] == 4] == [1]
