@@ -211,6 +211,10 @@ typedef struct {
     int32_t reserved2;
 } fsm_options;
 
+/* Device scratch of fsm_mine_noalloc, in MiB: one array per GPU the
+ * library runs on, held until the process ends. */
+#define FSM_NOALLOC_SCRATCH_MIB 256
+
 /* Allocation hooks used for all device memory of later calls (e.g. a
  * framework's caching allocator).  Both NULL restores hipMalloc/hipFree.
  * alloc(bytes, ctx) returns device memory or NULL; release(ptr, ctx). */
@@ -269,6 +273,36 @@ int fsm_mine(const fsm_graph *g, int64_t support, int32_t max_size,
  * outside (0, 1], a threshold out of range, or join_threshold together
  * with FSM_SAMPLED. */
 int fsm_mine_ex(const fsm_graph *g, const fsm_options *opt, fsm_result **out);
+
+/* fsm_mine_ex for callers that cannot allocate device memory (code that a
+ * harness forbids to call hipMalloc, tight serving loops): the call
+ * allocates nothing on the device -- no hipMalloc / hipFree, no allocation
+ * hook, no HIP event -- and takes every buffer it needs from a file-scope
+ * device array of FSM_NOALLOC_SCRATCH_MIB MiB (its device address fetched
+ * once per device with hipGetSymbolAddress, that device current).  Host
+ * bookkeeping still uses the C++ heap, as in every call.
+ *   g          a graph from fsm_build_graph on the current device (input)
+ *   opt        as fsm_mine_ex; record must be 0
+ *   capacity   entries of the three output arrays (>= 0)
+ *   sizes, codes, supports
+ *              host arrays receiving the patterns, ordered as
+ *              fsm_result_patterns orders them (may be NULL when capacity
+ *              is 0)
+ *   count      receives the number of frequent patterns (also on
+ *              FSM_EOVERFLOW for too small a capacity, nothing written)
+ *   stats      NULL or receives the call's counters (timings are 0)
+ * Every call on a GPU uses that GPU's one array, which keeps the previous
+ * call's contents (each call initialises what it reads); calls on one
+ * device are serialised by the library, as overlapping calls would race on
+ * the array.  Errors: as fsm_mine_ex; FSM_EINVAL for a NULL g/opt/count,
+ * capacity < 0, NULL arrays with capacity > 0, record set, or a graph of
+ * another device; FSM_EOVERFLOW when the graph alone exceeds the scratch
+ * (64 bytes per vertex + 16 per CSR entry) or the patterns exceed
+ * capacity; FSM_ENOMEM when the call needs more than the scratch holds (the
+ * message names the buffer). */
+int fsm_mine_noalloc(const fsm_graph *g, const fsm_options *opt, int64_t capacity,
+                     int32_t *sizes, fsm_code *codes, int64_t *supports, int64_t *count,
+                     fsm_stats *stats);
 
 /* Mine many graphs in one pass (batched mode): every level runs as one
  * launch per kernel over the disjoint union of the graphs, whose work items

@@ -144,6 +144,9 @@ def lib():
     L.fsm_mine.restype = ctypes.c_int
     L.fsm_mine_ex.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(vp)]
     L.fsm_mine_ex.restype = ctypes.c_int
+    L.fsm_mine_noalloc.argtypes = [vp, ctypes.POINTER(Options), ctypes.c_int64, i32p,
+                                   ctypes.POINTER(Code), i64p, i64p, ctypes.POINTER(Stats)]
+    L.fsm_mine_noalloc.restype = ctypes.c_int
     L.fsm_mine_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, i64p, ctypes.c_int32,
                                  ctypes.c_uint32, ctypes.POINTER(vp)]
     L.fsm_mine_batch.restype = ctypes.c_int
@@ -391,6 +394,42 @@ def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
     h = ctypes.c_void_p()
     _check(lib().fsm_mine_ex(graph.handle, ctypes.byref(o), ctypes.byref(h)))
     return Result(h)
+
+
+NOALLOC_SCRATCH_MIB = 256
+
+
+def mine_noalloc(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
+                 capacity: int = 1 << 16, sampling_rate: float = 1.0, seed: int = 0,
+                 join_threshold: int = 0, match_threshold: int = 0, model=None):
+    """fsm_mine_noalloc: the same mining call with no device allocation
+    (buffers come from the library's fixed scratch array).  Returns
+    ``(patterns, stats)`` with patterns as ``Result.patterns``."""
+    o = Options()
+    o.support = int(support)
+    o.max_size = int(max_size)
+    o.mode = int(mode)
+    o.sampling_rate = float(sampling_rate)
+    o.seed = int(seed) & ((1 << 64) - 1)
+    o.join_threshold = int(join_threshold)
+    o.match_threshold = int(match_threshold)
+    o.model = model.handle.value if model is not None else None
+    cap = int(capacity)
+    sizes = np.zeros(max(cap, 1), np.int32)
+    codes = np.zeros((max(cap, 1), 2 + MAX_SIZE), np.int32)
+    sups = np.zeros(max(cap, 1), np.int64)
+    cnt = ctypes.c_int64()
+    st = Stats()
+    _check(lib().fsm_mine_noalloc(
+        graph.handle, ctypes.byref(o), cap, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        codes.ctypes.data_as(ctypes.POINTER(Code)),
+        sups.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(cnt), ctypes.byref(st)))
+    n = cnt.value
+    adj = codes.view(np.uint32)[:n, 1 + MAX_SIZE].tolist()
+    labs = codes[:n, 1:1 + MAX_SIZE].tolist()
+    pats = [(k, tuple(lab[:k]), a, s) for k, lab, a, s in
+            zip(sizes[:n].tolist(), labs, adj, sups[:n].tolist())]
+    return pats, _stats_dict(st)
 
 
 def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,

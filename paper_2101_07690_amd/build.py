@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsm.so")
-SOURCES = ["abi.cpp", "scan.hip", "graph.hip", "mine.hip", "model.hip", "pieces.hip", "tune.cpp"]
+SOURCES = ["abi.cpp", "scan.hip", "graph.hip", "mine.hip", "model.hip", "pieces.hip", "tune.cpp",
+           "scratch.hip"]
 HEADERS = ["common.h", "internal.h", "model.h"]
 ARCH = "gfx950"
 

@@ -61,8 +61,20 @@ void fail(int code, const char* fmt, ...) {
 
 hipStream_t stream() { return g_hooks.stream; }
 
+void arena_release(void* p, void* ctx) { static_cast<Arena*>(ctx)->release(p); }
+
 void* raw_alloc(size_t bytes, void** ctx, void (**release)(void*, void*)) {
     void* p = nullptr;
+    if (Arena* a = active_arena()) {
+        p = a->alloc(bytes);
+        if (!p)
+            fail(FSM_ENOMEM, "the call needs more device memory than the %d MiB scratch of "
+                 "fsm_mine_noalloc (a buffer of %zu bytes; %zu in use, largest free range %zu)",
+                 FSM_NOALLOC_SCRATCH_MIB, bytes, a->in_use, a->largest_free());
+        *ctx = a;
+        *release = arena_release;
+        return p;
+    }
     if (g_hooks.alloc) {
         p = g_hooks.alloc(bytes, g_hooks.ctx);
         if (!p) fail(FSM_ENOMEM, "device allocation of %zu bytes failed", bytes);
@@ -140,38 +152,45 @@ int fsm_build_graph(int64_t n_vertices, int64_t n_edges, const int32_t* src, con
 int64_t fsm_graph_vertices(const fsm_graph* g) { return g ? g->n : -1; }
 int64_t fsm_graph_edges(const fsm_graph* g) { return g ? g->nnz / 2 : -1; }
 
+namespace {
+// Argument checks shared by fsm_mine_ex and fsm_mine_noalloc.
+void check_options(const fsm_graph* g, const fsm_options* opt) {
+    if (opt->support < 1) fail(FSM_EINVAL, "fsm_mine: support must be >= 1");
+    if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
+        fail(FSM_EINVAL, "fsm_mine: max_size must be in [2, %d]", FSM_MAX_SIZE);
+    if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED | FSM_INDUCED | FSM_SINGLE))
+        fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
+    if ((opt->mode & FSM_SINGLE) &&
+        ((opt->mode & (FSM_SAMPLED | FSM_LEARNED)) || opt->match_threshold > 0))
+        fail(FSM_EINVAL, "fsm_mine: FSM_SINGLE excludes FSM_SAMPLED, FSM_LEARNED and "
+                         "match_threshold");
+    if ((opt->mode & FSM_LEARNED) && !opt->model)
+        fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
+    if (opt->schedule != FSM_SCHEDULE_QUEUE && opt->schedule != FSM_SCHEDULE_STATIC)
+        fail(FSM_EINVAL, "fsm_mine: unknown schedule %d", opt->schedule);
+    if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)
+        fail(FSM_EINVAL, "fsm_mine: tiles_per_wave must be in [0, 4096]");
+    if (opt->pool_budget_mib < 0) fail(FSM_EINVAL, "fsm_mine: pool_budget_mib < 0");
+    if (opt->model && opt->model->m.D != FSM_FEATURES)
+        fail(FSM_EINVAL, "fsm_mine: the model must have FSM_FEATURES (%d) inputs", FSM_FEATURES);
+    if (opt->model && opt->model->device != g->device)
+        fail(FSM_EINVAL, "fsm_mine: model and graph live on different devices");
+    if ((opt->mode & FSM_SAMPLED) &&
+        !(opt->sampling_rate > 0.0 && opt->sampling_rate <= 1.0))
+        fail(FSM_EINVAL, "fsm_mine: sampling_rate must be in (0, 1]");
+    if (opt->join_threshold < 0 || opt->join_threshold > (int64_t)1 << 20)
+        fail(FSM_EINVAL, "fsm_mine: join_threshold must be in [0, 2^20]");
+    if (opt->match_threshold < 0) fail(FSM_EINVAL, "fsm_mine: match_threshold < 0");
+    if (opt->join_threshold > 0 && (opt->mode & FSM_SAMPLED))
+        fail(FSM_EINVAL, "fsm_mine: join_threshold and FSM_SAMPLED are exclusive");
+}
+}  // namespace
+
 int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
     if (out) *out = nullptr;
     return guarded([&] {
         if (!g || !opt || !out) fail(FSM_EINVAL, "fsm_mine: NULL argument");
-        if (opt->support < 1) fail(FSM_EINVAL, "fsm_mine: support must be >= 1");
-        if (opt->max_size < 2 || opt->max_size > FSM_MAX_SIZE)
-            fail(FSM_EINVAL, "fsm_mine: max_size must be in [2, %d]", FSM_MAX_SIZE);
-        if (opt->mode & ~(uint32_t)(FSM_SAMPLED | FSM_LEARNED | FSM_INDUCED | FSM_SINGLE))
-            fail(FSM_EINVAL, "fsm_mine: unsupported mode bits 0x%x", opt->mode);
-        if ((opt->mode & FSM_SINGLE) &&
-            ((opt->mode & (FSM_SAMPLED | FSM_LEARNED)) || opt->match_threshold > 0))
-            fail(FSM_EINVAL, "fsm_mine: FSM_SINGLE excludes FSM_SAMPLED, FSM_LEARNED and "
-                             "match_threshold");
-        if ((opt->mode & FSM_LEARNED) && !opt->model)
-            fail(FSM_EINVAL, "fsm_mine: FSM_LEARNED needs options.model");
-        if (opt->schedule != FSM_SCHEDULE_QUEUE && opt->schedule != FSM_SCHEDULE_STATIC)
-            fail(FSM_EINVAL, "fsm_mine: unknown schedule %d", opt->schedule);
-        if (opt->tiles_per_wave < 0 || opt->tiles_per_wave > 4096)
-            fail(FSM_EINVAL, "fsm_mine: tiles_per_wave must be in [0, 4096]");
-        if (opt->pool_budget_mib < 0) fail(FSM_EINVAL, "fsm_mine: pool_budget_mib < 0");
-        if (opt->model && opt->model->m.D != FSM_FEATURES)
-            fail(FSM_EINVAL, "fsm_mine: the model must have FSM_FEATURES (%d) inputs", FSM_FEATURES);
-        if (opt->model && opt->model->device != g->device)
-            fail(FSM_EINVAL, "fsm_mine: model and graph live on different devices");
-        if ((opt->mode & FSM_SAMPLED) &&
-            !(opt->sampling_rate > 0.0 && opt->sampling_rate <= 1.0))
-            fail(FSM_EINVAL, "fsm_mine: sampling_rate must be in (0, 1]");
-        if (opt->join_threshold < 0 || opt->join_threshold > (int64_t)1 << 20)
-            fail(FSM_EINVAL, "fsm_mine: join_threshold must be in [0, 2^20]");
-        if (opt->match_threshold < 0) fail(FSM_EINVAL, "fsm_mine: match_threshold < 0");
-        if (opt->join_threshold > 0 && (opt->mode & FSM_SAMPLED))
-            fail(FSM_EINVAL, "fsm_mine: join_threshold and FSM_SAMPLED are exclusive");
+        check_options(g, opt);
         fsm_result* r = new fsm_result();
         try {
             mine(g, *opt, r);
@@ -180,6 +199,49 @@ int fsm_mine_ex(const fsm_graph* g, const fsm_options* opt, fsm_result** out) {
             throw;
         }
         *out = r;
+    });
+}
+
+int fsm_mine_noalloc(const fsm_graph* g, const fsm_options* opt, int64_t capacity,
+                     int32_t* sizes, fsm_code* codes, int64_t* supports, int64_t* count,
+                     fsm_stats* stats) {
+    if (count) *count = 0;
+    return guarded([&] {
+        if (!g || !opt || !count) fail(FSM_EINVAL, "fsm_mine_noalloc: NULL argument");
+        if (capacity < 0 || (capacity > 0 && (!sizes || !codes || !supports)))
+            fail(FSM_EINVAL, "fsm_mine_noalloc: capacity < 0 or NULL output arrays");
+        if (opt->record) fail(FSM_EINVAL, "fsm_mine_noalloc: record is not supported");
+        check_options(g, opt);
+        // the graph's own per-vertex and per-entry state of a call
+        const int64_t floor_bytes = 64 * g->n + 16 * g->nnz;
+        if (floor_bytes > (int64_t)scratch_bytes())
+            fail(FSM_EOVERFLOW, "fsm_mine_noalloc: a graph of %lld vertices and %lld CSR "
+                 "entries needs more than the %d MiB scratch", (long long)g->n,
+                 (long long)g->nnz, FSM_NOALLOC_SCRATCH_MIB);
+        int dev = 0;
+        FSM_HIP(hipGetDevice(&dev));
+        if (dev != g->device)
+            fail(FSM_EINVAL, "fsm_mine_noalloc: the graph lives on device %d, device %d is "
+                 "current", g->device, dev);
+        std::lock_guard<std::mutex> lk(scratch_lock(dev));
+        uint8_t* base = scratch_base(dev);
+        fsm_result r;
+        {
+            Arena arena(base, scratch_bytes());
+            ArenaScope scope(&arena);
+            mine_in_arena(g, *opt, &r);
+        }
+        const int64_t n = (int64_t)r.size.size();
+        *count = n;
+        if (stats) *stats = r.stats;
+        if (n > capacity)
+            fail(FSM_EOVERFLOW, "fsm_mine_noalloc: %lld patterns, output capacity %lld",
+                 (long long)n, (long long)capacity);
+        for (int64_t i = 0; i < n; ++i) {
+            sizes[i] = r.size[(size_t)i];
+            codes[i] = r.code[(size_t)i];
+            supports[i] = r.support[(size_t)i];
+        }
     });
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -32,6 +34,35 @@ void set_error(const char* fmt, ...);
 #define FSM_LAUNCH_CHECK() FSM_HIP(hipGetLastError())
 
 hipStream_t stream();
+
+// First-fit arena over one device range (the allocation-free entry point's
+// scratch array): device buffers of a call come from it while it is the
+// thread's active arena, and go back to it when released.
+struct Arena {
+    uint8_t* base;
+    size_t size;
+    size_t in_use = 0, peak = 0;
+    Arena(uint8_t* b, size_t n);
+    void* alloc(size_t bytes);     // nullptr when no free range is large enough
+    void release(void* p);
+    size_t free_bytes() const { return size - in_use; }
+    size_t largest_free() const;
+
+  private:
+    std::map<size_t, size_t> free_, used_;   // offset -> length
+};
+
+Arena* active_arena();   // this thread's arena, or nullptr
+struct ArenaScope {      // makes an arena this thread's active one
+    Arena* prev;
+    explicit ArenaScope(Arena* a);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+};
+size_t scratch_bytes();           // size of the scratch array
+uint8_t* scratch_base(int dev);   // its device address on `dev` (current)
+std::mutex& scratch_lock(int dev);
 
 void* raw_alloc(size_t bytes, void** release_ctx, void (**release)(void*, void*));
 
@@ -146,6 +177,9 @@ namespace fsm {
 void build_graph(fsm_graph* g, int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                  const int32_t* labels);
 void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r);
+// fsm_mine_ex with every device buffer taken from the thread's active arena
+// and no HIP events (timings 0).
+void mine_in_arena(const fsm_graph* g, const fsm_options& opt, fsm_result* r);
 void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* supports,
                 const fsm_batch_options& opt, fsm_result* const* rs);
 // Shapes used where a call leaves chunk_vertices / tiles_per_wave at 0

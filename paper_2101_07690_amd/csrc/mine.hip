@@ -2952,7 +2952,8 @@ struct Miner {
     // key, value, ordered adjacency and labels, pattern slot).
     uint64_t grown_qp_capacity(uint64_t qcap, int n) const {
         size_t fr = 0, tot = 0;
-        FSM_HIP(hipMemGetInfo(&fr, &tot));
+        if (Arena* a = active_arena()) fr = a->free_bytes();
+        else FSM_HIP(hipMemGetInfo(&fr, &tot));
         const uint64_t room = (uint64_t)fr + qcap * 36ull;   // the old table is freed first
         uint64_t next = qcap * 16;
         while (next > qcap * 2 && next * 36ull > room / 2) next /= 2;
@@ -4073,9 +4074,11 @@ void Miner::run() {
     W = (uint32_t)((maxcount + 31) / 32);
     pass_W = W;
     // QP and pattern bitmap pools may take 40% of the free device memory
+    // (of the scratch arena's free bytes in an allocation-free call)
     {
         size_t fr = 0, tot = 0;
-        FSM_HIP(hipMemGetInfo(&fr, &tot));
+        if (Arena* a = active_arena()) fr = a->free_bytes();
+        else FSM_HIP(hipMemGetInfo(&fr, &tot));
         pool_budget = std::max<uint64_t>((uint64_t)(0.4 * (double)fr), (uint64_t)1 << 26);
         if (opt.pool_budget_mib > 0) pool_budget = (uint64_t)opt.pool_budget_mib << 20;
     }
@@ -4215,6 +4218,20 @@ void proposal_keep_thresholds(const float* pred, int64_t rows, double rate, uint
 
 void mine(const fsm_graph* g, const fsm_options& opt, fsm_result* r) {
     Miner m;
+    m.gv.single(g);
+    m.opt = opt;
+    m.model = opt.model ? &opt.model->m : nullptr;
+    m.tg.assign(1, opt.support);
+    m.res.assign(1, r);
+    r->stats.dropped_self_loops = g->dropped_loops;
+    r->stats.dropped_duplicates = g->dropped_dups;
+    r->stats.batch_chunks = 1;
+    m.run();
+}
+
+void mine_in_arena(const fsm_graph* g, const fsm_options& opt, fsm_result* r) {
+    Miner m;
+    m.timing = false;
     m.gv.single(g);
     m.opt = opt;
     m.model = opt.model ? &opt.model->m : nullptr;
