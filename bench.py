@@ -167,6 +167,13 @@ def batch_comparison(fsm, synth):
 
     passes = lambda rs: sum(r.stats["levels"][n]["domain_passes"] for r in rs
                             for n in r.stats["levels"] if n >= 4)
+    cap = per_chunk(res)
+    capture = {"chunks": len(cap),
+               "captured_levels": sum(st.stats["captured_levels"] for st in cap),
+               "captured_graphs": res[0].stats["captured_graphs"],
+               "level_fallbacks": res[0].stats["level_fallbacks"],
+               "host_syncs_per_chunk": round(sum(st.stats["host_syncs"] for st in cap) /
+                                             max(1, len(cap)), 1)}
     model.close()
     fsm.reset_tuning()
     for g in graphs:
@@ -188,6 +195,7 @@ def batch_comparison(fsm, synth):
             "training_s": round(t_train, 3),
             "tuned": tuned, "tuning_s": round(t_tune, 1),
             "tuning_candidates_ms": [[c, t, round(ms, 1)] for c, t, ms in cands],
+            "captured_last_levels": capture,
             "exact_match_plain": same}
 
 
@@ -362,6 +370,8 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    # device memory of every call comes from PyTorch's caching allocator
+    fsm.use_torch_allocator(True)
     w = synth.workload(args.workload)
     t, smax = w["support"], w["max_size"]
     print(f"[bench] workload {args.workload}: n={w['n']} m={w['m']} t={t} s_max={smax}",

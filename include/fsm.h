@@ -158,7 +158,16 @@ typedef struct {
     int32_t batch_chunks;          /* chunks of the call (1 for fsm_mine) */
     int32_t batch_splits;          /* chunks split after a table or memory
                                       overflow */
-    int32_t reserved0;
+    int32_t captured_levels;       /* levels of this pass run as one replay of
+                                      a captured HIP graph (batched calls:
+                                      the last join level of a chunk) */
+    int32_t captured_graphs;       /* batched calls: distinct level shapes
+                                      captured (each replayed across the
+                                      chunks of that shape) */
+    int32_t level_fallbacks;       /* captured levels rerun with eager
+                                      launches after a table overflow */
+    int64_t host_syncs;            /* host waits on the device in this pass
+                                      (for a batch: in its chunk) */
 } fsm_stats;
 
 /* Options of fsm_mine_ex.  Zero-initialise, then set fields. */
@@ -342,7 +351,12 @@ typedef struct {
                                    steps at learning rate lr) */
     int32_t train_steps;
     float lr;
-    int32_t reserved1;
+    int32_t eager_levels;       /* 1: every level of every chunk with eager
+                                   kernel launches; 0: the last join level
+                                   of each chunk as one replay of a HIP graph
+                                   captured per level shape (tables sized up
+                                   front, one host wait; a table overflow
+                                   reruns the level eagerly) */
     int64_t pool_budget_mib;    /* as fsm_options */
 } fsm_batch_options;
 

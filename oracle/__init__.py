@@ -61,6 +61,13 @@ def _load():
     lib.oracle_count_connected.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p,
                                            i32p, ctypes.c_int32]
     lib.oracle_count_connected.restype = ctypes.c_int64
+    lib.oracle_graph_new.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i32p]
+    lib.oracle_graph_new.restype = ctypes.c_void_p
+    lib.oracle_graph_support.argtypes = [ctypes.c_void_p, ctypes.c_int32, i32p, ctypes.c_uint32,
+                                         ctypes.c_int64, ctypes.c_int32]
+    lib.oracle_graph_support.restype = ctypes.c_int64
+    lib.oracle_graph_free.argtypes = [ctypes.c_void_p]
+    lib.oracle_graph_free.restype = None
     _lib = lib
     return lib
 
@@ -145,3 +152,43 @@ def count_connected(n_vertices, src, dst, size):
 def pair_index(i, j, n):
     """Bit position of the unordered pair (i<j), row-major upper triangle."""
     return i * n - i * (i + 1) // 2 + (j - i - 1)
+
+
+class Graph:
+    """A normalised input graph kept for many exact support queries."""
+
+    def __init__(self, n_vertices, src, dst, labels):
+        lib = _load()
+        s, sp = _arr(src)
+        d, dp = _arr(dst)
+        lab, lp = _arr(labels)
+        self._h = lib.oracle_graph_new(int(n_vertices), int(s.size), sp, dp, lp)
+        if not self._h:
+            raise ValueError("oracle_graph_new rejected its input")
+
+    def support(self, plabels, padj, t=0, induced=False):
+        """Exact MNI support of one connected pattern; with t > 0, -1 when
+        it is below t (the search stops early)."""
+        pl, plp = _arr(plabels)
+        r = _load().oracle_graph_support(self._h, len(plabels), plp, ctypes.c_uint32(padj),
+                                         int(t), 1 if induced else 0)
+        if r == -2:
+            raise ValueError("bad pattern")
+        return int(r)
+
+    def close(self):
+        if self._h:
+            _load().oracle_graph_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -623,6 +623,50 @@ int64_t oracle_pattern_support_ex(int64_t n_vertices, int64_t n_edges,
     return s;
 }
 
+/* A normalised input graph kept for many support queries (same graph
+ * normalisation and support search as above). */
+typedef struct oracle_graph {
+    ograph g;
+    obylabel bl;
+} oracle_graph;
+
+oracle_graph *oracle_graph_new(int64_t n_vertices, int64_t n_edges, const int32_t *src,
+                               const int32_t *dst, const int32_t *labels) {
+    oracle_graph *h = (oracle_graph *)calloc(1, sizeof(oracle_graph));
+    if (!h) return NULL;
+    if (graph_build(&h->g, n_vertices, n_edges, src, dst, labels) ||
+        bylabel_build(&h->g, &h->bl)) {
+        graph_free(&h->g);
+        free(h);
+        return NULL;
+    }
+    return h;
+}
+
+/* MNI support of one connected pattern on a kept graph; with t > 0 the
+ * search stops once the support is certainly below t and returns -1 (the
+ * exact support otherwise).  -2 on a bad pattern. */
+int64_t oracle_graph_support(const oracle_graph *h, int32_t n, const int32_t *plabels,
+                             uint32_t padj, int64_t t, int32_t induced) {
+    if (!h || n < 1 || n > OMAX) return -2;
+    opat p;
+    p.n = n;
+    memset(p.e, 0, sizeof(p.e));
+    for (int i = 0; i < n; i++) p.lab[i] = plabels[i];
+    for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++)
+            if (padj & (1u << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
+    if (!connected_mask(&p, (1u << n) - 1u)) return -2;
+    return support_of(&h->g, &h->bl, &p, t, induced);
+}
+
+void oracle_graph_free(oracle_graph *h) {
+    if (!h) return;
+    bylabel_free(&h->bl);
+    graph_free(&h->g);
+    free(h);
+}
+
 int64_t oracle_pattern_support(int64_t n_vertices, int64_t n_edges,
                                const int32_t *src, const int32_t *dst,
                                const int32_t *labels, int32_t n,

@@ -68,7 +68,8 @@ class Stats(ctypes.Structure):
                 ("level", LevelStats * (MAX_SIZE + 1)),
                 ("total_ms", ctypes.c_double), ("batch_chunk", ctypes.c_int32),
                 ("batch_chunks", ctypes.c_int32), ("batch_splits", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32)]
+                ("captured_levels", ctypes.c_int32), ("captured_graphs", ctypes.c_int32),
+                ("level_fallbacks", ctypes.c_int32), ("host_syncs", ctypes.c_int64)]
 
 
 TUNE_MAX = 16
@@ -86,7 +87,7 @@ class BatchOptions(ctypes.Structure):
                 ("tiles_per_wave", ctypes.c_int32), ("hash_capacity_min", ctypes.c_int64),
                 ("pattern_capacity_min", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("learn", ctypes.c_int32), ("train_steps", ctypes.c_int32),
-                ("lr", ctypes.c_float), ("reserved1", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("eager_levels", ctypes.c_int32),
                 ("pool_budget_mib", ctypes.c_int64)]
 
 
@@ -359,7 +360,9 @@ def _stats_dict(st):
             "dropped_duplicates": st.dropped_duplicates,
             "filtered_edges": st.filtered_edges, "levels": levels,
             "total_ms": st.total_ms, "batch_chunk": st.batch_chunk,
-            "batch_chunks": st.batch_chunks, "batch_splits": st.batch_splits}
+            "batch_chunks": st.batch_chunks, "batch_splits": st.batch_splits,
+            "captured_levels": st.captured_levels, "captured_graphs": st.captured_graphs,
+            "level_fallbacks": st.level_fallbacks, "host_syncs": st.host_syncs}
 
 
 def mine(graph: Graph, support: int, max_size: int, mode: int = FSM_PLAIN, *,
@@ -436,7 +439,7 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
                chunk_vertices: int = 0, disable_pruning: bool = False,
                hash_capacity_min: int = 0, pattern_capacity_min: int = 0, model=None,
                learn: bool = False, train_steps: int = 0, lr: float = 0.0,
-               tiles_per_wave: int = 0, pool_budget_mib: int = 0):
+               tiles_per_wave: int = 0, pool_budget_mib: int = 0, eager_levels: bool = False):
     """Mine several graphs in union passes of at most ``chunk_vertices``
     vertices (0: the library default); one Result per graph.  With a
     ``model``, FSM_LEARNED in ``mode`` sizes every chunk's join tables from
@@ -458,6 +461,7 @@ def mine_batch(graphs, supports, max_size: int, mode: int = FSM_BATCHED, *,
     o.pattern_capacity_min = int(pattern_capacity_min)
     o.model = model.handle.value if model is not None else None
     o.learn = 1 if learn else 0
+    o.eager_levels = 1 if eager_levels else 0
     o.train_steps = int(train_steps)
     o.lr = float(lr)
     _check(lib().fsm_mine_batch_ex(hs, n, sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

@@ -61,6 +61,11 @@ void fail(int code, const char* fmt, ...) {
 
 hipStream_t stream() { return g_hooks.stream; }
 
+int64_t& host_syncs() {
+    static thread_local int64_t n = 0;
+    return n;
+}
+
 void arena_release(void* p, void* ctx) { static_cast<Arena*>(ctx)->release(p); }
 
 void* raw_alloc(size_t bytes, void** ctx, void (**release)(void*, void*)) {

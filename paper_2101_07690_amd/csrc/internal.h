@@ -107,24 +107,33 @@ struct DBuf {
     }
 };
 
+// Host waits on the device made by this thread (stream or event
+// synchronisations), counted for the call statistics.
+int64_t& host_syncs();
+
+inline void sync_stream(hipStream_t s) {
+    ++host_syncs();
+    FSM_HIP(hipStreamSynchronize(s));
+}
+
 template <class T>
 void to_host(std::vector<T>& h, const T* d, size_t count) {
     h.resize(count);
     if (count) FSM_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, stream()));
-    FSM_HIP(hipStreamSynchronize(stream()));
+    sync_stream(stream());
 }
 
 template <class T>
 void to_host_into(T* h, const T* d, size_t count) {
     if (count) FSM_HIP(hipMemcpyAsync(h, d, count * sizeof(T), hipMemcpyDeviceToHost, stream()));
-    FSM_HIP(hipStreamSynchronize(stream()));
+    sync_stream(stream());
 }
 
 template <class T>
 T scalar_to_host(const T* d) {
     T v;
     FSM_HIP(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, stream()));
-    FSM_HIP(hipStreamSynchronize(stream()));
+    sync_stream(stream());
     return v;
 }
 

@@ -26,6 +26,9 @@
 // position), and the MNI support is the smallest orbit popcount.  The QP
 // value word then holds VALID | FREQ | 3-bit orbit slot per position.
 #include <algorithm>
+#include <array>
+#include <map>
+#include <memory>
 #include <atomic>
 #include <deque>
 #include <chrono>
@@ -249,30 +252,39 @@ __device__ __forceinline__ int64_t frequent_slot(const Rec& R, uint64_t key) {
     return (R.q.kv[2 * s + 1] & FREQ) ? s : -1;
 }
 
-// Adjacency test through per-vertex neighbour hash tables: vertex b owns a
-// linear-probing table of its G_f neighbours, pow2 slots >= 2*deg(b), at
-// tab[off[b] .. off[b+1]), empty slots -1.  A wave probing one vertex b for
-// many x stays within b's table (a few cache lines).
+// Adjacency test through per-vertex neighbour tables: vertex b owns a
+// two-choice cuckoo table of its G_f neighbours, nb(b) = pow2 >= deg(b)
+// buckets of two slots (load <= 1/2) at tab[off[b] .. off[b+1]), empty
+// slots -1.  A neighbour x sits in bucket h1(x) or h2(x), so a test reads
+// two 8-byte buckets -- no probe loop, the same work on every lane -- and a
+// wave testing one vertex b for many x stays within b's table.
 struct NbrHash {
-    const uint32_t* off;   // n + 1
-    const int32_t* tab;
+    const uint32_t* off;   // n + 1, in buckets
+    const int2* tab;
 };
 
-__device__ __forceinline__ uint32_t nbr_hash(int32_t x) {
+__host__ __device__ __forceinline__ uint32_t nbr_hash(int32_t x) {
     uint32_t h = (uint32_t)x * 0x9E3779B1u;
     return h ^ (h >> 15);
 }
 
+__host__ __device__ __forceinline__ uint32_t nbr_hash2(int32_t x) {
+    uint32_t h = ((uint32_t)x ^ 0x5bd1e995u) * 0x85EBCA77u;
+    return h ^ (h >> 13);
+}
+
+__device__ __forceinline__ bool in_bucket(int2 b, int32_t x) { return b.x == x || b.y == x; }
+
+// b's table holds x (nb = its bucket count, o its first bucket)
+__device__ __forceinline__ bool nbr_has(const int2* tab, uint32_t o, uint32_t nb, int32_t x) {
+    const int2 p = tab[o + (nbr_hash(x) & (nb - 1))];
+    const int2 q = tab[o + (nbr_hash2(x) & (nb - 1))];
+    return in_bucket(p, x) || in_bucket(q, x);
+}
+
 __device__ __forceinline__ bool has_edge(const NbrHash& H, int32_t b, int32_t x) {
-    const uint32_t o = H.off[b], cap = H.off[b + 1] - o;
-    if (!cap) return false;
-    uint32_t h = nbr_hash(x) & (cap - 1);
-    for (;;) {   // load <= 1/2: an empty slot ends every probe
-        const int32_t v = H.tab[o + h];
-        if (v == x) return true;
-        if (v < 0) return false;
-        h = (h + 1) & (cap - 1);
-    }
+    const uint32_t o = H.off[b], nb = H.off[b + 1] - o;
+    return nb != 0 && nbr_has(H.tab, o, nb, x);
 }
 
 // Vertex-induced mode: graph edges between frequent-label vertices whose
@@ -368,35 +380,71 @@ __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t*
 }
 
 // neighbour-table sizes: pow2 >= 2*deg, 0 for isolated vertices
-__global__ void k_nbr_sizes(const int32_t* row, int64_t n, int64_t* cap) {
+// Buckets of each vertex's neighbour table: the smallest power of two >=
+// deg (two slots each), times 2^grow[v] after failed builds.
+__global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, int64_t* nb) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = row[v + 1] - row[v];
         int64_t c = 0;
         if (d > 0) {
             c = 1;
-            while (c < 2 * d) c <<= 1;
+            while (c < d) c <<= 1;
+            c <<= grow[v];
         }
-        cap[v] = c;
+        nb[v] = c;
     }
 }
 
+// One thread per vertex: cuckoo insertion of its neighbours (a displaced
+// key moves to its other bucket); a vertex whose chain exceeds the bound is
+// marked in `failed` and rebuilt with twice the buckets.
+constexpr int CUCKOO_STEPS = 512;
+
 __global__ void k_nbr_fill(const int32_t* row, const int32_t* col, int64_t n, const int64_t* off,
-                           int64_t total, uint32_t* off32, int32_t* tab) {
+                           int64_t total, uint32_t* off32, int2* tab, uint8_t* failed,
+                           unsigned* nfailed) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
          v += (int64_t)gridDim.x * blockDim.x) {
         if (v == n) { off32[n] = (uint32_t)total; continue; }
         const int64_t o = off[v];
         off32[v] = (uint32_t)o;
-        const uint32_t cap = (uint32_t)((v + 1 < n ? off[v + 1] : total) - o);
-        for (uint32_t s = 0; s < cap; ++s) tab[o + s] = -1;
-        for (int32_t e = row[v]; e < row[v + 1]; ++e) {
-            const int32_t x = col[e];
-            uint32_t h = nbr_hash(x) & (cap - 1);
-            while (tab[o + h] >= 0) h = (h + 1) & (cap - 1);
-            tab[o + h] = x;
+        const uint32_t nb = (uint32_t)((v + 1 < n ? off[v + 1] : total) - o);
+        int2* t = tab + o;
+        for (uint32_t b = 0; b < nb; ++b) t[b] = make_int2(-1, -1);
+        bool ok = true;
+        for (int32_t e = row[v]; e < row[v + 1] && ok; ++e) {
+            int32_t x = col[e];
+            uint32_t b = nbr_hash(x) & (nb - 1);
+            int step = 0;
+            for (;; ++step) {
+                if (t[b].x < 0) { t[b].x = x; break; }
+                if (t[b].y < 0) { t[b].y = x; break; }
+                const uint32_t b2 = (nbr_hash(x) & (nb - 1)) == b ? (nbr_hash2(x) & (nb - 1))
+                                                                 : (nbr_hash(x) & (nb - 1));
+                if (b2 != b) {
+                    if (t[b2].x < 0) { t[b2].x = x; break; }
+                    if (t[b2].y < 0) { t[b2].y = x; break; }
+                }
+                if (step >= CUCKOO_STEPS) { ok = false; break; }
+                // displace a key of bucket b2 (alternating slots) and carry it on
+                int32_t y;
+                if (step & 1) { y = t[b2].y; t[b2].y = x; } else { y = t[b2].x; t[b2].x = x; }
+                x = y;
+                b = b2;
+            }
+        }
+        if (!ok) {
+            failed[v] = 1;
+            atomicAdd(nfailed, 1u);
         }
     }
+}
+
+__global__ void k_grow_failed(const uint8_t* failed, int64_t n, uint8_t* grow) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        if (failed[v]) grow[v] += 1;
 }
 
 // pieces rooted at k: centre pairs C(d,2) plus one slot per (u in N(k),
@@ -794,10 +842,11 @@ __device__ __forceinline__ bool f3_at(const uint8_t* f3, int F, int t, int a, in
 // in vertex-induced mode induced subgraphs of the input graph.  A k-centre
 // slot holds the wedge u-k-w and, when u ~ w, the triangle; a k-leaf slot
 // the wedge k-u-w.  `bytes` counts the adjacency probes.
+template <class Count>
 __device__ __forceinline__ uint32_t piece_types(const uint8_t* f3, int F, const NbrHash& nh,
                                                 const NbrHash& xh, int induced, bool centre,
                                                 int32_t k, int32_t u, int32_t w, int lk, int lu,
-                                                int lw, unsigned long long& bytes) {
+                                                int lw, Count& bytes) {
     uint32_t types = 0;
     if (centre) {
         const bool fw = f3_at(f3, F, 0, lk, lu, lw);
@@ -1647,44 +1696,38 @@ constexpr uint32_t RANK_MASK = (1u << 26) - 1;
 // Two-entry per-lane caches: QP key -> slot, and the QP slots (+1) whose
 // joining-vertex / piece bits this lane already set in the current tile.
 struct LaneCache {
-    uint64_t k0, v0, k1, v1;   // QP lookups (persist across tiles)
-    uint64_t b0, b1;           // bits done in this tile
+    uint64_t k0, k1;   // QP keys looked up last (persist across tiles)
+    uint32_t v0, v1;   // their slots (tables hold at most 2^31 slots)
+    uint32_t b0, b1;   // slots + 1 whose piece bits this lane set in the tile
 };
 
 // Adjacency of every parent vertex except k with the piece's two new
 // vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  The parent vertex
-// is the same across the wave, so all lanes probe the same small table; the
-// first probes are issued before any is resolved.
+// is the same across the wave, so all lanes read the same small table; each
+// test is two bucket reads, all issued before any is compared.
 template <int N>
 __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int32_t (&cv)[N],
                                                      int i) {
     constexpr int M = N - 2;
-    uint32_t o[M], cap[M], h[2 * M];
-    int32_t got[2 * M];
+    const int32_t u = cv[M], w = cv[M + 1];
+    const uint32_t hu1 = nbr_hash(u), hu2 = nbr_hash2(u), hw1 = nbr_hash(w), hw2 = nbr_hash2(w);
+    int2 bu1[M], bu2[M], bw1[M], bw2[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        o[j] = H.off[cv[j]];
-        cap[j] = H.off[cv[j] + 1] - o[j];
-    }
-#pragma unroll
-    for (int b = 0; b < 2 * M; ++b) {
-        const int j = b >> 1;
-        h[b] = nbr_hash(cv[M + (b & 1)]) & (cap[j] - 1);
-        got[b] = (j != i && cap[j]) ? H.tab[o[j] + h[b]] : -1;
+        const uint32_t o = H.off[cv[j]], nb = H.off[cv[j] + 1] - o;
+        const int2 none = make_int2(-1, -1);
+        const bool live = j != i && nb != 0;
+        const uint32_t m = nb - 1;
+        bu1[j] = live ? H.tab[o + (hu1 & m)] : none;
+        bu2[j] = live ? H.tab[o + (hu2 & m)] : none;
+        bw1[j] = live ? H.tab[o + (hw1 & m)] : none;
+        bw2[j] = live ? H.tab[o + (hw2 & m)] : none;
     }
     uint32_t ec = 0;
 #pragma unroll
-    for (int b = 0; b < 2 * M; ++b) {
-        const int j = b >> 1;
-        if (j == i) continue;
-        const int32_t x = cv[M + (b & 1)];
-        int32_t v = got[b];
-        uint32_t hh = h[b];
-        while (v >= 0 && v != x) {
-            hh = (hh + 1) & (cap[j] - 1);
-            v = H.tab[o[j] + hh];
-        }
-        if (v == x) ec |= 1u << b;
+    for (int j = 0; j < M; ++j) {
+        if (in_bucket(bu1[j], u) || in_bucket(bu2[j], u)) ec |= 1u << (2 * j);
+        if (in_bucket(bw1[j], w) || in_bucket(bw2[j], w)) ec |= 1u << (2 * j + 1);
     }
     return ec;
 }
@@ -1696,6 +1739,7 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
 // excluded from the enumeration up front.
 template <int N, bool EXTRA>
 __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f3,
+                                             const uint16_t* __restrict__ dtab,
                                              const int32_t (&cv)[N],
                                              const int32_t (&lr)[N], int i, uint32_t types,
                                              uint32_t ec, uint64_t PA, uint64_t L, int32_t pslot,
@@ -1767,7 +1811,7 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
 #pragma unroll
             for (int b = 0; b < 2 * M; ++b)
                 if ((sub >> b) & 1u) radj |= cm[b];
-            if (a.dtab[radj] == want) {
+            if (dtab[radj] == want) {
                 const uint64_t key = kbase | sub;
                 int64_t s;
                 if (key == c.k0) {
@@ -1787,14 +1831,15 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                     s = qp_slot(*a.rec, key, L, A);
                     if (s >= 0) {
                         c.k1 = c.k0; c.v1 = c.v0;
-                        c.k0 = key; c.v0 = (uint64_t)s;
+                        c.k0 = key; c.v0 = (uint32_t)s;
                     }
                 }
                 if (s >= 0 && EXTRA && (a.porb || a.qcnt)) {
                     // candidate-bitmap passes: per-QP counts, bits in the
                     // (pattern, orbit) bitmap of each position
                     if (a.qcnt) atomicAdd(&a.qcnt[s], 1ull);
-                    const bool once = (uint64_t)s + 1 != c.b0 && (uint64_t)s + 1 != c.b1;
+                    const uint32_t s1 = (uint32_t)s + 1u;
+                    const bool once = s1 != c.b0 && s1 != c.b1;
 #pragma unroll
                     for (int p = 0; p < N; ++p) {
                         if ((p >= M || p == i) && !once) continue;
@@ -1804,20 +1849,21 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                     }
                     if (once) {
                         c.b1 = c.b0;
-                        c.b0 = (uint64_t)s + 1;
+                        c.b0 = s1;
                     }
                 } else if (s >= 0) {
                     const uint32_t W = a.W;
                     uint32_t* base = a.bits + (uint64_t)s * N * W;
                     // joining vertex and piece vertices: once per QP per tile
-                    if ((uint64_t)s + 1 != c.b0 && (uint64_t)s + 1 != c.b1) {
+                    const uint32_t s1 = (uint32_t)s + 1u;
+                    if (s1 != c.b0 && s1 != c.b1) {
 #pragma unroll
                         for (int p = 0; p < N; ++p) {
                             if (p < M && p != i) continue;
                             set_bit_in(base + (uint64_t)p * W, lr[p], a.rbase, W);
                         }
                         c.b1 = c.b0;
-                        c.b0 = (uint64_t)s + 1;
+                        c.b0 = s1;
                     }
 #pragma unroll
                     for (int p = 0; p < M; ++p) {
@@ -1839,13 +1885,21 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
 // EXTRA = false builds the exact edge-induced join without the sampling and
 // vertex-induced paths (fewer live registers).
 template <int N, bool EXTRA>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles(
-    TileArgs a) {
+__device__ __forceinline__ void join_tiles(const TileArgs& a) {
     constexpr int M = N - 2;
+    // sizes 4 and 5: the dissection table (2^(n(n-1)/2) entries, at most
+    // 2 KB) is read from LDS
+    constexpr int DT_LDS = N <= 5 ? 1 << (N * (N - 1) / 2) : 1;
+    __shared__ uint16_t sdt[DT_LDS];
+    if (N <= 5) {
+        for (int x = threadIdx.x; x < DT_LDS; x += TPB) sdt[x] = a.dtab[x];
+        __syncthreads();
+    }
+    const uint16_t* __restrict__ dtab = N <= 5 ? sdt : a.dtab;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (TPB / 64);
     unsigned long long emit = 0, cands = 0, bytes = 0;
-    LaneCache c{EMPTY_KEY, 0, EMPTY_KEY, 0, 0, 0};
+    LaneCache c{EMPTY_KEY, EMPTY_KEY, 0, 0, 0, 0};
     int64_t g = 0;
     int64_t run_item = -1, run_sum = 0;   // recording: children of the current item run
     for (int64_t t = a.queue ? -1 : wave_id_global() - nw;;) {
@@ -1997,7 +2051,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
                 lr[M] = lru;
                 lr[M + 1] = lrw;
-                got = children_tile<N, EXTRA>(a, f3, cv, lr, i, ty, ec, PA, Lc, pslot, lu, lw, c);
+                got = children_tile<N, EXTRA>(a, f3, dtab, cv, lr, i, ty, ec, PA, Lc, pslot, lu, lw,
+                                              c);
                 emit += (unsigned long long)got;
                 bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
             }
@@ -2024,6 +2079,15 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         if (tc) atomicAdd(&a.ctr[1], (unsigned long long)tc);
         if (tb) atomicAdd(&a.ctr[3], (unsigned long long)tb);
     }
+}
+
+// The domain pass takes its arguments from device memory: the fields are
+// read where they are used instead of being held (and spilled) in scalar
+// registers for the whole kernel.
+template <int N, bool EXTRA>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles_p(
+    const TileArgs* __restrict__ a) {
+    join_tiles<N, EXTRA>(*a);
 }
 
 // Domain pass of the single-vertex join, tiled like the two-vertex one:
@@ -2068,7 +2132,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     constexpr int M = N - 1;
     const int lane = threadIdx.x & 63;
     unsigned long long emit = 0, cands = 0, bytes = 0;
-    LaneCache c{EMPTY_KEY, 0, EMPTY_KEY, 0, 0, 0};
+    LaneCache c{EMPTY_KEY, EMPTY_KEY, 0, 0, 0, 0};
     int64_t g = 0;
     for (;;) {
         unsigned long long nt = 0;
@@ -2201,7 +2265,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                             sl = qp_slot(*a.rec, key, Lc, A);
                             if (sl >= 0) {
                                 c.k1 = c.k0; c.v1 = c.v0;
-                                c.k0 = key; c.v0 = (uint64_t)sl;
+                                c.k0 = key; c.v0 = (uint32_t)sl;
                             }
                         }
                         if (sl >= 0) {
@@ -2214,11 +2278,12 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                 return a.bits + ((uint64_t)sl * N + p) * a.W;
                             };
                             // k and u: once per QP per tile
-                            if ((uint64_t)sl + 1 != c.b0 && (uint64_t)sl + 1 != c.b1) {
+                            const uint32_t s1 = (uint32_t)sl + 1u;
+                            if (s1 != c.b0 && s1 != c.b1) {
                                 if (uint32_t* b = bm(i)) set_bit_in(b, lr[i], a.rbase, a.W);
                                 if (uint32_t* b = bm(M)) set_bit_in(b, lr[M], a.rbase, a.W);
                                 c.b1 = c.b0;
-                                c.b0 = (uint64_t)sl + 1;
+                                c.b0 = s1;
                             }
 #pragma unroll
                             for (int j = 0; j < M; ++j) {
@@ -2282,7 +2347,7 @@ struct CanonArgs {
 
 // One thread per QP: canonical form (the one isomorphism computation of
 // its group), pattern slot, and the orbit slot of each QP position.
-__global__ void k_qp_canon(CanonArgs a) {
+__device__ __forceinline__ void qp_canon(const CanonArgs& a) {
     for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < a.slots;
          s += (uint64_t)gridDim.x * blockDim.x) {
         if (a.q.kv[2 * s] == EMPTY_KEY) continue;
@@ -2318,7 +2383,7 @@ struct MergeArgs {
 };
 
 // OR every QP position bitmap into its (pattern, orbit) bitmap.
-__global__ __launch_bounds__(TPB) void k_qp_merge(MergeArgs a) {
+__device__ __forceinline__ void qp_merge(const MergeArgs& a) {
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t nw = (uint64_t)gridDim.x * (TPB / 64);
     for (uint64_t it = (uint64_t)wave_id_global(); it < a.items; it += nw) {
@@ -2351,7 +2416,7 @@ struct MniArgs {
 
 // One wavefront per pattern slot: add the popcount of each orbit bitmap
 // of this pass's rank slice to the orbit's domain size.
-__global__ __launch_bounds__(TPB) void k_orbit_count(MniArgs a, int64_t* ocnt) {
+__device__ __forceinline__ void orbit_count(const MniArgs& a, int64_t* ocnt) {
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t nw = (uint64_t)gridDim.x * (TPB / 64);
     for (uint64_t s = (uint64_t)wave_id_global(); s < a.slots; s += nw) {
@@ -2372,7 +2437,7 @@ __global__ __launch_bounds__(TPB) void k_orbit_count(MniArgs a, int64_t* ocnt) {
 
 // MNI support of every pattern slot (Section 2.2): the smallest orbit
 // domain; one thread per slot.
-__global__ void k_mni(MniArgs a, const int64_t* ocnt) {
+__device__ __forceinline__ void mni(const MniArgs& a, const int64_t* ocnt) {
     for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < a.slots;
          s += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t key = a.c.kv[2 * s];
@@ -2394,6 +2459,88 @@ __global__ void k_mni(MniArgs a, const int64_t* ocnt) {
         }
     }
 }
+
+__global__ void k_qp_canon(CanonArgs a) { qp_canon(a); }
+__global__ __launch_bounds__(TPB) void k_qp_merge(MergeArgs a) { qp_merge(a); }
+__global__ __launch_bounds__(TPB) void k_orbit_count(MniArgs a, int64_t* ocnt) {
+    orbit_count(a, ocnt);
+}
+__global__ void k_mni(MniArgs a, const int64_t* ocnt) { mni(a, ocnt); }
+
+// ------------------------------------------------ captured join levels
+//
+// A batched call runs the last join level of each chunk as one replay of a
+// HIP graph: reset of the level's tables, domain pass, canonical forms,
+// merge into (pattern, orbit) bitmaps, orbit popcounts and MNI.  Every
+// kernel of the graph reads its arguments from a device descriptor, so one
+// instantiated graph serves every chunk whose level has the same shape
+// (size, table capacities, bitmap words); the host writes the chunk's
+// descriptor, replays, and synchronises once to read the overflow flags and
+// the patterns.  Nothing is cleared by memset nodes: k_level_reset fills.
+struct LevelDesc {
+    TileArgs t;
+    CanonArgs ca;
+    MergeArgs ma;
+    MniArgs m;
+    int64_t* ocnt;
+    uint32_t* pool;            // QP-position bitmaps
+    uint32_t* ppool;           // pattern-orbit bitmaps
+    unsigned long long* counters;
+    uint32_t* flags;
+    uint64_t qslots, cslots, pool_words, ppool_words, ocnt_items;
+};
+
+// Grid-stride fill of n words (16-byte stores where aligned).
+__device__ __forceinline__ void fill_words(uint32_t* p, uint64_t n, uint64_t tid, uint64_t nth) {
+    const uint64_t n4 = ((uintptr_t)p & 15) ? 0 : n / 4;
+    uint4* q = reinterpret_cast<uint4*>(p);
+    for (uint64_t x = tid; x < n4; x += nth) q[x] = make_uint4(0, 0, 0, 0);
+    for (uint64_t x = n4 * 4 + tid; x < n; x += nth) p[x] = 0;
+}
+
+__global__ void k_level_reset(const LevelDesc* __restrict__ d) {
+    const QPTab& q = d->ca.q;
+    const CodeTab& c = d->ca.c;
+    const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = tid; x < d->qslots; x += nth) {
+        q.kv[2 * x] = EMPTY_KEY;
+        q.kv[2 * x + 1] = 0;
+        q.adj[x] = 0;
+        q.lab[x] = 0;
+        q.pat[x] = 0;
+    }
+    for (uint64_t x = tid; x < d->cslots; x += nth) {
+        c.kv[2 * x] = EMPTY_KEY;
+        c.kv[2 * x + 1] = 0;
+        c.info[x] = 0;
+        c.sup[x] = 0;
+    }
+    fill_words(d->pool, d->pool_words, tid, nth);
+    fill_words(d->ppool, d->ppool_words, tid, nth);
+    for (uint64_t x = tid; x < d->ocnt_items; x += nth) d->ocnt[x] = 0;
+    if (tid == 0) {
+        *q.count = 0;
+        *c.count = 0;
+        *d->m.out_n = 0;
+        *d->flags = 0;
+        for (int k = 0; k < 4; ++k) d->counters[k] = 0;
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles_d(
+    const LevelDesc* __restrict__ d) {
+    join_tiles<N, false>(d->t);
+}
+__global__ void k_qp_canon_d(const LevelDesc* __restrict__ d) { qp_canon(d->ca); }
+__global__ __launch_bounds__(TPB) void k_qp_merge_d(const LevelDesc* __restrict__ d) {
+    qp_merge(d->ma);
+}
+__global__ __launch_bounds__(TPB) void k_orbit_count_d(const LevelDesc* __restrict__ d) {
+    orbit_count(d->m, d->ocnt);
+}
+__global__ void k_mni_d(const LevelDesc* __restrict__ d) { mni(d->m, d->ocnt); }
 
 // Levels whose domains take more than one rank slice keep bitmaps only for
 // candidate patterns.  The automorphisms of a subgraph map an orbit o onto
@@ -2747,7 +2894,7 @@ struct GraphView {
         }
         k_fill_i32<<<1, 1, 0, st>>>(urow.p + n, 1, (int32_t)nnz);
         FSM_LAUNCH_CHECK();
-        FSM_HIP(hipStreamSynchronize(st));
+        sync_stream(st);
         row = urow.p;
         col = ucol.p;
         lab = ulab.p;
@@ -2855,10 +3002,85 @@ struct Timer {
     float stop() {
         if (!a) return 0.f;
         FSM_HIP(hipEventRecord(b, s));
+        ++host_syncs();
         FSM_HIP(hipEventSynchronize(b));
         float ms = 0.f;
         FSM_HIP(hipEventElapsedTime(&ms, a, b));
         return ms;
+    }
+};
+
+// Captured join levels of one batched call: a stream of its own for the
+// replays, and per level size a device descriptor and an instantiated
+// graph.  Every kernel of the graph takes its table sizes from the
+// descriptor and strides over them with the persistent grid, so one graph
+// serves every chunk whatever its table capacities and bitmap widths.
+template <int N>
+void enqueue_level(hipStream_t s, const LevelDesc* d, unsigned grid) {
+    k_level_reset<<<grid, TPB, 0, s>>>(d);
+    k_join_tiles_d<N><<<grid, TPB, 0, s>>>(d);
+    k_qp_canon_d<<<grid, TPB, 0, s>>>(d);
+    k_qp_merge_d<<<grid, TPB, 0, s>>>(d);
+    k_orbit_count_d<<<grid, TPB, 0, s>>>(d);
+    k_mni_d<<<grid, TPB, 0, s>>>(d);
+}
+
+struct LevelGraphs {
+    struct Entry {
+        DBuf<LevelDesc> desc;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    std::map<std::array<uint64_t, 2>, std::unique_ptr<Entry>> cache;
+    int32_t fallbacks = 0;
+    int64_t replays = 0;
+
+    LevelGraphs() = default;
+    LevelGraphs(const LevelGraphs&) = delete;
+    LevelGraphs& operator=(const LevelGraphs&) = delete;
+    ~LevelGraphs() {
+        for (auto& kv : cache) {
+            if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+            if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
+        }
+        if (ev) (void)hipEventDestroy(ev);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    void init() {
+        if (cs) return;
+        FSM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        FSM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    // the graph of a level size, captured on first use
+    Entry& get(int n, unsigned grid) {
+        const std::array<uint64_t, 2> key{(uint64_t)n, (uint64_t)grid};
+        auto it = cache.find(key);
+        if (it != cache.end()) return *it->second;
+        auto e = std::make_unique<Entry>();
+        e->desc.alloc(1);
+        FSM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        switch (n) {
+            case 4: enqueue_level<4>(cs, e->desc.p, grid); break;
+            case 5: enqueue_level<5>(cs, e->desc.p, grid); break;
+            case 6: enqueue_level<6>(cs, e->desc.p, grid); break;
+            default: {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                fail(FSM_EINVAL, "no captured level of size %d", n);
+            }
+        }
+        const hipError_t le = hipGetLastError();
+        const hipError_t ce = hipStreamEndCapture(cs, &e->graph);
+        if (le != hipSuccess || ce != hipSuccess)
+            fail(FSM_EDEVICE, "capture of the size-%d level failed: %s", n,
+                 hipGetErrorString(le != hipSuccess ? le : ce));
+        FSM_HIP(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+        Entry& ref = *e;
+        cache.emplace(key, std::move(e));
+        return ref;
     }
 };
 
@@ -2875,11 +3097,11 @@ struct Miner {
     DBuf<int32_t> frow, fcol;             // G_f
     int64_t fnnz = 0;
     DBuf<uint32_t> nhoff;
-    DBuf<int32_t> nhtab;
+    DBuf<int2> nhtab;
     NbrHash nh() const { return NbrHash{nhoff.p, nhtab.p}; }
     // vertex-induced mode: tables of the edges outside G_f (empty: none)
     DBuf<uint32_t> xhoff;
-    DBuf<int32_t> xhtab;
+    DBuf<int2> xhtab;
     NbrHash xh() const { return NbrHash{xhoff.p, xhtab.p}; }
     DBuf<uint64_t> mthr;            // matching sampling thresholds
     Sampling sampling() const {
@@ -2893,7 +3115,7 @@ struct Miner {
     void st_pieces(int n, const Sampling& smp, DBuf<int64_t>& cnt, DBuf<int64_t>& off,
                    DBuf<uint64_t>& key, DBuf<uint8_t>& code);
     void neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
-                          DBuf<int32_t>& tab);
+                          DBuf<int2>& tab);
     DBuf<int64_t> npieces;
     DBuf<int32_t> leafoff;
     DBuf<uint8_t> f3;
@@ -2908,15 +3130,21 @@ struct Miner {
     DBuf<uint32_t> vinfo;
     DBuf<Rec> drec;     // device copy of the recording context of the join
     Rec hrec{};
+    DBuf<TileArgs> dtile;   // device copy of the domain pass's arguments
+    TileArgs htile{};
     DBuf<unsigned long long> counters;   // [emitted, candidates, work queue, bytes]
     DBuf<uint32_t> flags;
     uint32_t W = 1;
     unsigned grid_persistent = 1024;
     bool timing = true;          // per-level HIP-event timings (off: 0 ms)
+    LevelGraphs* lg = nullptr;   // batched calls: captured last join levels
+    LevelDesc hdesc{};           // host copy of the descriptor being replayed
+    int32_t captured = 0;        // levels of this pass run as graph replays
     Level lv[FSM_MAX_SIZE + 1];
     std::vector<fsm_result*> res;         // one per graph
 
     uint64_t qhint[FSM_MAX_SIZE + 1] = {};   // first QP table size per level (0: default)
+    uint64_t chint[FSM_MAX_SIZE + 1] = {};   // captured levels: pattern table size
     const Model* model = nullptr;          // FSM_LEARNED: sizes the join tables
     std::vector<float> rx, rt;             // recorded work-item rows (features, targets)
     std::vector<int32_t> rl, rg;           // their join size and graph id
@@ -3008,11 +3236,11 @@ struct Miner {
         const int64_t ranks = (int64_t)W * 32;
         uint32_t w0 = W;
         // child keys of a later join carry this level's QP slots in 29 bits;
-        // the last level's slots go into no key (its limits are the 32-bit
-        // QP counter and the int32 pattern slots)
+        // the last level's slots go into no key (the joins' lane caches hold
+        // slots in 32 bits, so a table has at most 2^31 slots)
         const bool parent_level = (opt.mode & FSM_SINGLE) ? L.n + 1 <= opt.max_size
                                                           : L.n + 2 <= opt.max_size;
-        const uint64_t qcap_max = parent_level ? (1ull << 29) : (1ull << 32);
+        const uint64_t qcap_max = parent_level ? (1ull << 29) : (1ull << 31);
         for (int attempt = 0;; ++attempt) {
             L.st.domain_passes = attempt + 1;
             L.st.qp_capacity = (int64_t)qcap;
@@ -3046,7 +3274,7 @@ struct Miner {
             if (!(f & OVF_QP)) break;
             if (attempt >= (opt.force_overflow ? 16 : 8))
                 fail(FSM_EOVERFLOW, "QP table kept overflowing at size %d", L.n);
-            qcap = grown_qp_capacity(qcap, L.n);
+            qcap = std::min(grown_qp_capacity(qcap, L.n), std::max(qcap * 2, qcap_max));
         }
         std::vector<unsigned long long> cnt;
         to_host(cnt, counters.p, 4);
@@ -3268,6 +3496,8 @@ struct Miner {
     void proposal_thresholds(const ItemRows& IR, const float* y, int64_t nitems,
                              DBuf<uint64_t>& thr);
 
+    template <class MakeArgs>
+    bool captured_level(Level& L, MakeArgs&& make_args);
     void run();
     void level2();
     void build_gf();
@@ -3276,6 +3506,103 @@ struct Miner {
     void join_single(int n);
     void emit_results();
 };
+
+// The last join level of a batch chunk as one graph replay.  Tables are
+// sized up front (the level's hint: cost model or earlier chunks) and the
+// code table as large as the QP table, so only a QP-table overflow can
+// spoil the replay; then the level is rerun with eager launches from a
+// grown table.  Returns false when the level must run eagerly.
+template <class MakeArgs>
+bool Miner::captured_level(Level& L, MakeArgs&& make_args) {
+    const int n = L.n;
+    const uint64_t qcap = opt.force_overflow ? qcap0() : std::max(qcap0(), qhint[n]);
+    // pattern table: the density earlier chunks needed, never above the QP
+    // table (every pattern has a quick pattern)
+    const uint64_t ccap = opt.force_overflow ? 2 : std::min(qcap, std::max<uint64_t>(chint[n], 1024));
+    const uint32_t Wq = W;
+    const uint64_t words = qcap * (uint64_t)n * Wq;
+    const uint64_t pwords = ccap * (uint64_t)n * Wq;
+    if (words * sizeof(uint32_t) > pool_budget / 2 || qcap > (1ull << 29)) return false;
+    lg->init();
+    LevelGraphs::Entry& e = lg->get(n, grid_persistent);
+    L.tab.alloc(qcap, ccap);
+    if (words > pool_words) { pool.alloc(words); pool_words = words; }
+    if (pwords > ppool_words) { ppool.alloc(pwords); ppool_words = pwords; }
+    DBuf<int64_t> ocnt((size_t)(ccap * n));
+    DBuf<uint64_t> okey((size_t)ccap);
+    DBuf<int64_t> osup((size_t)ccap);
+    DBuf<unsigned> on(1);
+    pass_W = Wq;
+    pass_rbase = 0;
+    pass_porb = nullptr;
+    pass_qcnt = nullptr;
+    const Rec R = rec(L);
+    pass_W = W;
+    LevelDesc& d = hdesc;
+    d.t = make_args(R);
+    const QPTab q{L.tab.qkv.p, qcap - 1, L.tab.qadj.p, L.tab.qlab.p, L.tab.qpat.p, L.tab.qcount.p};
+    const CodeTab ct{L.tab.ckv.p, ccap - 1, L.tab.cinfo.p, L.tab.csup.p, L.tab.ccount.p};
+    d.ca = CanonArgs{q, ct, flags.p, n, qcap, (uint64_t)g->ngraphs};
+    d.ma = MergeArgs{q, pool.p, ppool.p, Wq, 0, Wq, n, qcap * (uint64_t)n};
+    d.m = MniArgs{ct, {ppool.p, lrank.p, Wq, 0}, n, ccap, okey.p, osup.p, on.p, (unsigned)ccap};
+    d.ocnt = ocnt.p;
+    d.pool = pool.p;
+    d.ppool = ppool.p;
+    d.counters = counters.p;
+    d.flags = flags.p;
+    d.qslots = qcap;
+    d.cslots = ccap;
+    d.pool_words = words;
+    d.ppool_words = pwords;
+    d.ocnt_items = ccap * (uint64_t)n;
+    FSM_HIP(hipMemcpyAsync(e.desc.p, &d, sizeof(LevelDesc), hipMemcpyHostToDevice, st));
+    FSM_HIP(hipEventRecord(lg->ev, st));
+    FSM_HIP(hipStreamWaitEvent(lg->cs, lg->ev, 0));
+    {
+        Timer gt(timing, lg->cs);
+        gt.start();
+        FSM_HIP(hipGraphLaunch(e.exec, lg->cs));
+        L.st.join_ms = gt.stop();
+    }
+    sync_stream(lg->cs);
+    ++lg->replays;
+    const uint32_t f = scalar_to_host(flags.p);
+    if (f & (ERR_MISSING | ERR_FILL))
+        fail(FSM_EDEVICE, "internal consistency check failed at size %d (flags %u)", n, f);
+    if (f & ERR_GRAPH) fail(FSM_EDEVICE, "a quick pattern at size %d names no graph of the call", n);
+    if (f & ERR_BATCH) fail(FSM_EUNSUPPORTED, "batches of several graphs support sizes up to 6");
+    if (f & (OVF_QP | OVF_CODE)) {
+        if (f & OVF_QP) qhint[n] = grown_qp_capacity(qcap, n);
+        if (f & OVF_CODE) chint[n] = std::min(qcap, ccap * 4);
+        L.tab = Tables();
+        ++lg->fallbacks;
+        return false;
+    }
+    std::vector<unsigned long long> cnt;
+    to_host(cnt, counters.p, 4);
+    const unsigned nqp = scalar_to_host(L.tab.qcount.p);
+    const unsigned npat = scalar_to_host(on.p);
+    L.st.domain_passes = 1;
+    L.st.qp_capacity = (int64_t)qcap;
+    L.st.emitted = (int64_t)cnt[0];
+    L.st.candidates = (int64_t)cnt[1];
+    L.st.algorithmic_bytes = (int64_t)cnt[3];
+    L.st.quick_patterns = nqp;
+    L.st.canonical_forms = nqp;
+    L.st.patterns = npat;
+    L.st.rank_slices = 1;
+    std::vector<uint64_t> hk;
+    std::vector<int64_t> hs;
+    to_host(hk, okey.p, npat);
+    to_host(hs, osup.p, npat);
+    L.freq.clear();
+    for (unsigned i = 0; i < npat; ++i)
+        if (hs[i] >= tg[graph_of(hk[i], n)]) L.freq.emplace_back(hk[i], hs[i]);
+    std::sort(L.freq.begin(), L.freq.end());
+    L.st.frequent = (int64_t)L.freq.size();
+    ++captured;
+    return true;
+}
 
 void Miner::level2() {
     Level& L = lv[2];
@@ -3335,18 +3662,30 @@ void Miner::build_gf() {
 
 // Per-vertex linear-probing neighbour tables of the CSR (row, col).
 void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
-                             DBuf<int32_t>& tab) {
+                             DBuf<int2>& tab) {
     const int64_t n = g->n;
-    DBuf<int64_t> cap((size_t)n + 1);
-    k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(row, n, cap.p);
-    FSM_LAUNCH_CHECK();
-    const int64_t total = scan_exclusive(cap.p, cap.p, n);
-    if (total >= (int64_t)UINT32_MAX) fail(FSM_EUNSUPPORTED, "neighbour tables exceed 2^32 slots");
-    off.alloc((size_t)n + 1);
-    tab.alloc((size_t)(total > 0 ? total : 1));
-    k_nbr_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(row, col, n, cap.p, total, off.p, tab.p);
-    FSM_LAUNCH_CHECK();
-    FSM_HIP(hipStreamSynchronize(st));
+    DBuf<int64_t> nb((size_t)n + 1);
+    DBuf<uint8_t> grow((size_t)n), failed((size_t)n);
+    DBuf<unsigned> nfailed(1);
+    grow.zero();
+    for (int attempt = 0;; ++attempt) {
+        k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(row, n, grow.p, nb.p);
+        FSM_LAUNCH_CHECK();
+        const int64_t total = scan_exclusive(nb.p, nb.p, n);
+        if (total >= (int64_t)UINT32_MAX)
+            fail(FSM_EUNSUPPORTED, "neighbour tables exceed 2^32 buckets");
+        off.alloc((size_t)n + 1);
+        tab.alloc((size_t)(total > 0 ? total : 1));
+        failed.zero();
+        nfailed.zero();
+        k_nbr_fill<<<grid_for(n + 1, TPB), TPB, 0, st>>>(row, col, n, nb.p, total, off.p, tab.p,
+                                                        failed.p, nfailed.p);
+        FSM_LAUNCH_CHECK();
+        if (scalar_to_host(nfailed.p) == 0) break;
+        if (attempt >= 8) fail(FSM_EDEVICE, "neighbour table construction kept failing");
+        k_grow_failed<<<grid_for(n, TPB), TPB, 0, st>>>(failed.p, n, grow.p);
+        FSM_LAUNCH_CHECK();
+    }
 }
 
 // Thresholds of every vertex's group of a fixed-size sample (Section 5):
@@ -3527,7 +3866,7 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
     }
     FSM_HIP(hipMemcpyAsync(G.toff.p + G.ngroups, &G.ntiles, sizeof(int64_t),
                            hipMemcpyHostToDevice, st));
-    FSM_HIP(hipStreamSynchronize(st));
+    sync_stream(st);
 }
 
 // Longest-processing-time order of the key groups for the work queue:
@@ -3578,7 +3917,7 @@ void Miner::order_groups(const Level& P, int M, const ItemRows& IR, const float*
     if (nt != G.ntiles) fail(FSM_EDEVICE, "tile count changed by reordering (%lld vs %lld)",
                              (long long)nt, (long long)G.ntiles);
     FSM_HIP(hipMemcpyAsync(G.toff.p + ng, &G.ntiles, sizeof(int64_t), hipMemcpyHostToDevice, st));
-    FSM_HIP(hipStreamSynchronize(st));
+    sync_stream(st);
 }
 
 // Sampling proposal: keep rate min(1, lambda / c_i) for work item i, where
@@ -3820,6 +4159,13 @@ void Miner::join(int n) {
     // sampling, vertex-induced and candidate-bitmap paths
     const bool extra = (opt.mode & (FSM_SAMPLED | FSM_INDUCED)) || ithr.p || smp.kthr ||
                        smp.ethr || smp.mthr;
+    // batched calls: the last level as a replay of its captured graph
+    if (lg && !extra && !ich.p && n + 2 > opt.max_size && n <= 6 && G.ntiles > 0 &&
+        captured_level(L, tile_args)) {
+        if (pred_raw > 0.0 && L.st.quick_patterns > 0)
+            model->calib[n] = (double)L.st.quick_patterns / pred_raw;
+        return;
+    }
     {
         Timer jt(timing, st);
         float join_total = 0.f;
@@ -3833,13 +4179,15 @@ void Miner::join(int n) {
             if (pass == 0) join_total = 0.f;   // a new attempt
             jt.start();
             if (G.ntiles > 0) {
-                TileArgs t = tile_args(R);
-                t.item_children = pass == 0 ? ich.p : nullptr;
-                const bool ex = extra || t.porb || t.qcnt;
+                htile = tile_args(R);
+                htile.item_children = pass == 0 ? ich.p : nullptr;
+                const bool ex = extra || htile.porb || htile.qcnt;
+                FSM_HIP(hipMemcpyAsync(dtile.p, &htile, sizeof(TileArgs), hipMemcpyHostToDevice,
+                                       st));
 #define FSM_TILES_CASE(NN)                                                          \
     case NN:                                                                        \
-        if (ex) k_join_tiles<NN, true><<<grid_persistent, TPB, 0, st>>>(t);          \
-        else k_join_tiles<NN, false><<<grid_persistent, TPB, 0, st>>>(t);            \
+        if (ex) k_join_tiles_p<NN, true><<<grid_persistent, TPB, 0, st>>>(dtile.p);  \
+        else k_join_tiles_p<NN, false><<<grid_persistent, TPB, 0, st>>>(dtile.p);    \
         break;
                 switch (n) {
                     FSM_TILES_CASE(4)
@@ -4028,6 +4376,7 @@ void Miner::emit_results() {
 
 void Miner::run() {
     auto t0 = std::chrono::steady_clock::now();
+    const int64_t syncs0 = host_syncs();
     st = stream();
     for (fsm_result* r : res) r->stats.max_size = opt.max_size;
     const int32_t G = g->ngraphs, NL = g->L;
@@ -4095,6 +4444,7 @@ void Miner::run() {
     k_vinfo<<<grid_for(g->n, TPB), TPB, 0, st>>>(vf.p, lrank.p, g->n, vinfo.p);
     FSM_LAUNCH_CHECK();
     drec.alloc(1);
+    dtile.alloc(1);
     counters.alloc(4);
     flags.alloc(1);
 
@@ -4170,7 +4520,11 @@ void Miner::run() {
     emit_results();
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (fsm_result* r : res) r->stats.total_ms = ms;
+    for (fsm_result* r : res) {
+        r->stats.total_ms = ms;
+        r->stats.captured_levels = captured;
+        r->stats.host_syncs = host_syncs() - syncs0;
+    }
 }
 
 }  // namespace
@@ -4289,8 +4643,10 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
     o.pattern_capacity_min = bo.pattern_capacity_min;
     // quick patterns per union vertex seen so far, per level: the next
     // chunk's tables start at that density (load <= 1/2, 25% slack)
-    double qpv[FSM_MAX_SIZE + 1] = {};
+    double qpv[FSM_MAX_SIZE + 1] = {};   // and canonical patterns per union vertex
+    double ppv[FSM_MAX_SIZE + 1] = {};
     int32_t chunk = 0, splits = 0;
+    LevelGraphs lgs;
     std::vector<int32_t> chunk_of((size_t)count, 0);
     while (!todo.empty()) {
         std::vector<int32_t> part = std::move(todo.front());
@@ -4306,8 +4662,11 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
         Miner m;
         m.opt = o;
         m.model = bo.model ? &bo.model->m : nullptr;
-        for (int n = 2; n <= FSM_MAX_SIZE; ++n)
+        if (!bo.eager_levels) m.lg = &lgs;
+        for (int n = 2; n <= FSM_MAX_SIZE; ++n) {
             if (qpv[n] > 0) m.qhint[n] = pow2_at_least((uint64_t)(2.5 * qpv[n] * (double)nv) + 16);
+            if (ppv[n] > 0) m.chint[n] = pow2_at_least((uint64_t)(2.5 * ppv[n] * (double)nv) + 16);
+        }
         try {
             m.gv.batch(pg.data(), (int32_t)pg.size());
             for (int32_t i : part) m.tg.push_back(supports[i]);
@@ -4316,7 +4675,7 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
         } catch (const Failure& f) {
             if ((f.code != FSM_EOVERFLOW && f.code != FSM_ENOMEM) || part.size() < 2) throw;
             (void)hipGetLastError();
-            FSM_HIP(hipStreamSynchronize(stream()));
+            sync_stream(stream());
             for (fsm_result* r : pr) *r = fsm_result();
             const size_t h = part.size() / 2;
             todo.push_front(std::vector<int32_t>(part.begin() + (long)h, part.end()));
@@ -4324,8 +4683,10 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
             ++splits;
             continue;
         }
-        for (int n = 2; n <= o.max_size; ++n)
+        for (int n = 2; n <= o.max_size; ++n) {
             qpv[n] = std::max(qpv[n], (double)m.lv[n].st.quick_patterns / (double)std::max<int64_t>(nv, 1));
+            ppv[n] = std::max(ppv[n], (double)m.lv[n].st.patterns / (double)std::max<int64_t>(nv, 1));
+        }
         // online learning: the next chunks are sized by a model that has
         // seen this chunk's work items
         if (bo.learn && bo.model && !m.rl.empty()) {
@@ -4345,6 +4706,8 @@ void mine_batch(const fsm_graph* const* gs, int32_t count, const int64_t* suppor
         rs[i]->stats.batch_chunk = chunk_of[(size_t)i];
         rs[i]->stats.batch_chunks = chunk;
         rs[i]->stats.batch_splits = splits;
+        rs[i]->stats.captured_graphs = (int32_t)lgs.cache.size();
+        rs[i]->stats.level_fallbacks = lgs.fallbacks;
     }
 }
 

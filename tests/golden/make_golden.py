@@ -23,6 +23,7 @@ CASES = [
     # the 1M-vertex, 37-label workload's generator at 1/10 scale (same
     # seeds, exponent, degree cap and label law; t = 2% of the vertices as
     # there), mined to its stated size 6
+    ("cl1m_tenth_t2000_s5", "cl1m", 2_000, 5, {"n": 100_000, "m": 1_200_000}),
     ("cl1m_tenth_t2000_s6", "cl1m", 2_000, 6, {"n": 100_000, "m": 1_200_000}),
 ]
 

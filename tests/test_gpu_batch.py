@@ -99,3 +99,50 @@ def test_tune_batch_picks_a_candidate_and_keeps_results():
         fsm.reset_tuning()
         for g in gs:
             g.close()
+
+
+def test_captured_levels_match_eager_and_replay_across_chunks():
+    """The last join level of every chunk runs as a replay of a HIP graph
+    captured per level shape.  Small chunks give many chunks of few shapes:
+    graphs are captured once per shape and replayed for the others, and the
+    results equal the eager launches and the plain per-graph calls."""
+    ws = [w for w in synth.batch_workload() if w["n"] < 4000][:40]
+    gs = [build(w["src"], w["dst"], w["vertex_labels"]) for w in ws]
+    sup = [w["support"] for w in ws]
+    try:
+        for smax in (4, 5):
+            print(f"captured levels smax={smax}", flush=True)
+            cap = fsm.mine_batch(gs, sup, smax, chunk_vertices=8192)
+            eager = fsm.mine_batch(gs, sup, smax, chunk_vertices=8192, eager_levels=True)
+            chunks = {r.stats["batch_chunk"]: r.stats for r in cap}
+            assert len(chunks) >= 4
+            replayed = sum(st["captured_levels"] for st in chunks.values())
+            assert replayed >= len(chunks) - cap[0].stats["level_fallbacks"]
+            assert 1 <= cap[0].stats["captured_graphs"] < replayed
+            assert all(r.stats["captured_levels"] == 0 for r in eager)
+            for g, s, a, b in zip(gs, sup, cap, eager):
+                assert a.patterns == b.patterns
+            for i in range(0, len(ws), 5):
+                assert cap[i].patterns == fsm.mine(gs[i], sup[i], smax).patterns
+            # no more host waits than the eager launches
+            syncs = lambda rs: sum({r.stats["batch_chunk"]: r.stats["host_syncs"]
+                                    for r in rs}.values())
+            assert 0 < syncs(cap) <= syncs(eager) + len(chunks)
+    finally:
+        for g in gs:
+            g.close()
+
+
+def test_captured_level_overflow_falls_back():
+    """A level whose table (forced to 2 slots) overflows inside the replay
+    is rerun eagerly from a grown table, with identical results."""
+    cases = [synth.tiny_graph(8500 + s, 9, 14, 2) for s in range(12)]
+    gs = [build(*c) for c in cases]
+    try:
+        a = fsm.mine_batch(gs, [1] * 12, 5, hash_capacity_min=2)
+        assert a[0].stats["level_fallbacks"] >= 1
+        for (s, d, lab), r in zip(cases, a):
+            assert r.patterns == oracle.mine(len(lab), s, d, lab, 1, 5)
+    finally:
+        for g in gs:
+            g.close()

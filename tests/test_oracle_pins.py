@@ -304,3 +304,18 @@ def test_repeated_pairs_do_not_inflate_a_star():
     assert sup[(2, 1)] == 4
     assert [p[3] for p in got if p[0] == 3] == [1]
     assert [p[3] for p in got if p[0] == 4] == [1]
+
+
+def test_kept_graph_support_queries_match_mining():
+    """oracle.Graph answers single-pattern queries with the same search the
+    miner uses: exact supports for every mined pattern, and -1 (below t)
+    exactly when a query's threshold exceeds the support."""
+    for seed in range(4):
+        s, t, lab = synth.tiny_graph(9300 + seed, 8, 12, 2)
+        want = oracle.mine(len(lab), s, t, lab, 1, 5)
+        with oracle.Graph(len(lab), s, t, lab) as g:
+            for n, labs, adj, sup in want:
+                assert g.support(labs, adj) == sup
+                assert g.support(labs, adj, t=sup) == sup
+                assert g.support(labs, adj, t=sup + 1) == -1
+                assert oracle.pattern_support(len(lab), s, t, lab, labs, adj) == sup
