@@ -2,18 +2,26 @@
 
 One step = one full fsm_mine call (sizes 2..max_size: labelled edges, size-3
 matching, every two-vertex join level, quick-pattern coding, canonical dedup,
-MNI domains, filtering, compaction) on a graph already resident in HBM.
+MNI domains, filtering, compaction) on a graph already resident in HBM; the
+headline workload is the 100k-vertex Chung-Lu graph (29 Zipf labels,
+t = 10000, sizes 2..5).
 
 Prints one JSON line.  ``value`` is embeddings extended per second: the
 subgraphs emitted by all join levels of one step divided by the step's wall
 time.  ``roofline`` covers the dominant kernel (the join level with the
-longest domain pass), timed with HIP events on its launch stream.
-``cpu_baseline`` is the single-thread CPU oracle on the same workload.
-``batch`` compares plain per-graph calls with batched+learned mining on the
-256-graph workload (same device, identical results required).
-``single_vertex`` mines the same graph by single-vertex exploration (the
-paper's baseline) and ``sampling`` with sampling thresholds ST 2..16,
-scored against the exact result.
+longest domain pass), timed with HIP events on its launch stream: it is
+bound by vector-instruction issue ("alu"), with measured HBM traffic and
+the L2-level algorithmic bytes beside it.  ``cpu_baseline`` is the
+single-thread CPU oracle's wall time on the same workload (host CPU model
+and core count stated).  ``small_config`` times the 3,300-vertex workload on
+both.  ``batch`` compares plain per-graph calls, batched mining with plain
+table sizing, and batched mining with a cost model trained on a disjoint
+batch, on the 256-graph workload (identical results required).
+``cost_model`` mines the 1M-vertex, 37-label workload to size 5 with plain
+and learned table sizing and checks it against the oracle's sampled exact
+supports.  ``single_vertex`` mines the headline graph by single-vertex
+exploration (the paper's baseline) and ``sampling`` with sampling
+thresholds ST 2..16, scored against the exact result.
 """
 import argparse
 import json
@@ -82,7 +90,7 @@ def join_roofline(results, dom, workload):
     nbytes = levels[dom]["algorithmic_bytes"]
     sec = ms / 1e3
     prof = profiled_counters(dom, workload)
-    kernel = f"k_join_tiles<{dom}, false> (domain pass)"
+    kernel = f"k_join_tiles_p<{dom}, false> (domain pass)"
     l2 = {"algorithmic_bytes": nbytes,
           "achieved_GBs": round(nbytes / sec / 1e9, 3) if sec > 0 else None,
           "note": "bytes the method must move; L2 serves them"}
@@ -283,6 +291,14 @@ def cost_model_leg(fsm, synth, max_size=5):
     plain, tp = timed()
     learned, tl = timed(mode=fsm.FSM_LEARNED, model=model)
     print(f"[bench] cl1m plain {tp:.2f} s, learned {tl:.2f} s", file=sys.stderr, flush=True)
+    # exact-match status: the oracle's supports of a seeded sample of
+    # patterns and of one-vertex extensions (tests/golden, oracle only)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "cl1m_sampled_t20000_s5.json")))
+    index = {(p[0], tuple(p[1]), p[2]): p[3] for p in plain.patterns}
+    entries = gold["sampled"] + [e for x in gold["extension_checks"] for e in x["extensions"]]
+    agree = sum(1 for n, labs, adj, sup in entries
+                if (index.get((n, tuple(labs), adj)) == sup if sup >= 0
+                    else (n, tuple(labs), adj) not in index))
     lv = lambda r, k: {n: r.stats["levels"][n][k] for n in r.stats["levels"] if n >= 4}
     out = {"workload": "cl1m", "max_size": max_size, "patterns": len(plain),
            "training_rows": int(len(rec.train_x)), "training_loss": round(loss, 4),
@@ -292,7 +308,9 @@ def cost_model_leg(fsm, synth, max_size=5):
            "rank_slices_plain": lv(plain, "rank_slices"),
            "rank_slices_learned": lv(learned, "rank_slices"),
            "qp_predicted": lv(learned, "qp_predicted"), "qp_actual": lv(plain, "quick_patterns"),
-           "exact_match_plain": plain.patterns == learned.patterns}
+           "exact_match_plain": plain.patterns == learned.patterns,
+           "oracle_sampled_checks": len(entries), "oracle_sampled_agree": agree,
+           "exact_match_oracle_sample": agree == len(entries)}
     model.close()
     g.close()
     return out
@@ -348,8 +366,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 256-graph plain vs batched+learned comparison")
-    ap.add_argument("--cost-model-leg", action="store_true",
-                    help="also mine the 1M-vertex, 37-label workload (sizes 2..5) with plain "
+    ap.add_argument("--no-cost-model-leg", action="store_true",
+                    help="skip the 1M-vertex, 37-label workload (sizes 2..5) mined with plain "
                          "and with learned table sizing")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-vertex exploration comparison")
@@ -411,7 +429,7 @@ def main():
     single = None if args.no_single else single_vertex_leg(fsm, g, t, smax, ref)
     sampled = None if args.no_sampling else sampling_leg(fsm, g, t, smax, ref)
     batch = None if args.no_batch else batch_comparison(fsm, synth)
-    learned = cost_model_leg(fsm, synth) if args.cost_model_leg else None
+    learned = None if args.no_cost_model_leg else cost_model_leg(fsm, synth)
 
     cpu = None
     exact = None

@@ -1796,8 +1796,11 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
         }
     }
     int got = 0;
-    for (int t = 0; t < 3; ++t) {
-        if (!((types >> t) & 1u)) continue;
+    // each lane walks its own piece types (nearly always one): a wave runs
+    // the body as often as its lane with the most types, not once per type
+    // any lane has
+    for (uint32_t pend = types; pend; pend &= pend - 1u) {
+        const int t = __builtin_ctz(pend);
         const uint32_t r0 =
             rpar | eku | (t == PIECE_KC ? ekw : (t == PIECE_KL ? euw : (ekw | euw)));
         const uint32_t allowed = t == PIECE_KL ? allow_kl : allow_both;
@@ -2528,19 +2531,6 @@ __global__ void k_level_reset(const LevelDesc* __restrict__ d) {
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles_d(
-    const LevelDesc* __restrict__ d) {
-    join_tiles<N, false>(d->t);
-}
-__global__ void k_qp_canon_d(const LevelDesc* __restrict__ d) { qp_canon(d->ca); }
-__global__ __launch_bounds__(TPB) void k_qp_merge_d(const LevelDesc* __restrict__ d) {
-    qp_merge(d->ma);
-}
-__global__ __launch_bounds__(TPB) void k_orbit_count_d(const LevelDesc* __restrict__ d) {
-    orbit_count(d->m, d->ocnt);
-}
-__global__ void k_mni_d(const LevelDesc* __restrict__ d) { mni(d->m, d->ocnt); }
 
 // Levels whose domains take more than one rank slice keep bitmaps only for
 // candidate patterns.  The automorphisms of a subgraph map an orbit o onto
@@ -3012,17 +3002,22 @@ struct Timer {
 
 // Captured join levels of one batched call: a stream of its own for the
 // replays, and per level size a device descriptor and an instantiated
-// graph.  Every kernel of the graph takes its table sizes from the
-// descriptor and strides over them with the persistent grid, so one graph
-// serves every chunk whatever its table capacities and bitmap widths.
+// graph of six kernel nodes: the table reset and the domain pass read their
+// arguments from the descriptor; the canonical-form, merge, orbit-count and
+// MNI nodes are the kernels of the eager path, whose arguments and grids
+// are set per chunk on the instantiated graph (hipGraphExecKernelNodeSetParams)
+// before it is replayed.
+constexpr unsigned CAPTURE_GRID = 1u << 14;
+
 template <int N>
-void enqueue_level(hipStream_t s, const LevelDesc* d, unsigned grid) {
-    k_level_reset<<<grid, TPB, 0, s>>>(d);
-    k_join_tiles_d<N><<<grid, TPB, 0, s>>>(d);
-    k_qp_canon_d<<<grid, TPB, 0, s>>>(d);
-    k_qp_merge_d<<<grid, TPB, 0, s>>>(d);
-    k_orbit_count_d<<<grid, TPB, 0, s>>>(d);
-    k_mni_d<<<grid, TPB, 0, s>>>(d);
+void enqueue_level(hipStream_t s, LevelDesc* d, unsigned grid) {
+    k_level_reset<<<CAPTURE_GRID, TPB, 0, s>>>(d);
+    k_join_tiles_p<N, false><<<grid, TPB, 0, s>>>(&d->t);
+    // placeholders: every replay sets these nodes' arguments first
+    k_qp_canon<<<1, TPB, 0, s>>>(CanonArgs{});
+    k_qp_merge<<<1, TPB, 0, s>>>(MergeArgs{});
+    k_orbit_count<<<1, TPB, 0, s>>>(MniArgs{}, nullptr);
+    k_mni<<<1, TPB, 0, s>>>(MniArgs{}, nullptr);
 }
 
 struct LevelGraphs {
@@ -3030,6 +3025,7 @@ struct LevelGraphs {
         DBuf<LevelDesc> desc;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
+        hipGraphNode_t canon = nullptr, merge = nullptr, orbit = nullptr, mni = nullptr;
     };
     hipStream_t cs = nullptr;
     hipEvent_t ev = nullptr;
@@ -3077,10 +3073,40 @@ struct LevelGraphs {
         if (le != hipSuccess || ce != hipSuccess)
             fail(FSM_EDEVICE, "capture of the size-%d level failed: %s", n,
                  hipGetErrorString(le != hipSuccess ? le : ce));
+        // the nodes whose arguments change per chunk, found by their kernel
+        size_t count = 0;
+        FSM_HIP(hipGraphGetNodes(e->graph, nullptr, &count));
+        std::vector<hipGraphNode_t> nodes(count);
+        FSM_HIP(hipGraphGetNodes(e->graph, nodes.data(), &count));
+        for (hipGraphNode_t nd : nodes) {
+            hipGraphNodeType ty;
+            FSM_HIP(hipGraphNodeGetType(nd, &ty));
+            if (ty != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams kp{};
+            FSM_HIP(hipGraphKernelNodeGetParams(nd, &kp));
+            if (kp.func == reinterpret_cast<void*>(&k_qp_canon)) e->canon = nd;
+            else if (kp.func == reinterpret_cast<void*>(&k_qp_merge)) e->merge = nd;
+            else if (kp.func == reinterpret_cast<void*>(&k_orbit_count)) e->orbit = nd;
+            else if (kp.func == reinterpret_cast<void*>(&k_mni)) e->mni = nd;
+        }
+        if (!e->canon || !e->merge || !e->orbit || !e->mni)
+            fail(FSM_EDEVICE, "captured size-%d level: kernel nodes not found", n);
         FSM_HIP(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
         Entry& ref = *e;
         cache.emplace(key, std::move(e));
         return ref;
+    }
+    // point a kernel node of the instantiated graph at new arguments
+    static void set_node(hipGraphExec_t exec, hipGraphNode_t nd, void* func, unsigned blocks,
+                         void** args) {
+        hipKernelNodeParams kp{};
+        kp.func = func;
+        kp.gridDim = dim3(blocks);
+        kp.blockDim = dim3(TPB);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        FSM_HIP(hipGraphExecKernelNodeSetParams(exec, nd, &kp));
     }
 };
 
@@ -3159,6 +3185,24 @@ struct Miner {
     };
     void item_rows(const Level& P, int n, ItemRows& IR);
 
+    // Release the bitmap pools of the previous level and size the budget of
+    // the next: QP and pattern bitmap pools may take 40% of the device
+    // memory free now (of the scratch arena's free bytes in an
+    // allocation-free call), counting the pools just released, which a
+    // caching allocator may keep.
+    void refresh_pool_budget() {
+        const uint64_t released = (pool_words + ppool_words) * sizeof(uint32_t);
+        pool.reset();
+        ppool.reset();
+        pool_words = ppool_words = 0;
+        size_t fr = 0, tot = 0;
+        if (Arena* a = active_arena()) fr = a->free_bytes();
+        else FSM_HIP(hipMemGetInfo(&fr, &tot));
+        const uint64_t avail = active_arena() ? (uint64_t)fr : (uint64_t)fr + released;
+        pool_budget = std::max<uint64_t>((uint64_t)(0.4 * (double)avail), (uint64_t)1 << 26);
+        if (opt.pool_budget_mib > 0) pool_budget = (uint64_t)opt.pool_budget_mib << 20;
+    }
+
     uint64_t qcap0() const {
         if (opt.force_overflow) return 2;
         uint64_t c = opt.hash_capacity_min > 0 ? (uint64_t)opt.hash_capacity_min : (1ull << 14);
@@ -3230,6 +3274,7 @@ struct Miner {
     // table.  launch(R, pass) runs the level's domain kernel.
     template <class Launch>
     void domain_level(Level& L, Launch&& launch) {
+        refresh_pool_budget();
         uint64_t qcap = L.tab.qcap ? L.tab.qcap
                                    : (opt.force_overflow ? qcap0() : std::max(qcap0(), qhint[L.n]));
         DBuf<unsigned long long> qcnt;
@@ -3515,6 +3560,7 @@ struct Miner {
 template <class MakeArgs>
 bool Miner::captured_level(Level& L, MakeArgs&& make_args) {
     const int n = L.n;
+    refresh_pool_budget();
     const uint64_t qcap = opt.force_overflow ? qcap0() : std::max(qcap0(), qhint[n]);
     // pattern table: the density earlier chunks needed, never above the QP
     // table (every pattern has a quick pattern)
@@ -3556,6 +3602,20 @@ bool Miner::captured_level(Level& L, MakeArgs&& make_args) {
     d.ppool_words = pwords;
     d.ocnt_items = ccap * (uint64_t)n;
     FSM_HIP(hipMemcpyAsync(e.desc.p, &d, sizeof(LevelDesc), hipMemcpyHostToDevice, st));
+    {
+        void* ca[] = {&d.ca};
+        void* ma[] = {&d.ma};
+        void* oa[] = {&d.m, &d.ocnt};
+        void* na[] = {&d.m, &d.ocnt};
+        LevelGraphs::set_node(e.exec, e.canon, reinterpret_cast<void*>(&k_qp_canon),
+                              grid_for((int64_t)qcap, TPB), ca);
+        LevelGraphs::set_node(e.exec, e.merge, reinterpret_cast<void*>(&k_qp_merge),
+                              grid_for((int64_t)(qcap * n), TPB / 64, 1u << 16), ma);
+        LevelGraphs::set_node(e.exec, e.orbit, reinterpret_cast<void*>(&k_orbit_count),
+                              grid_for((int64_t)ccap, TPB / 64, 1u << 16), oa);
+        LevelGraphs::set_node(e.exec, e.mni, reinterpret_cast<void*>(&k_mni),
+                              grid_for((int64_t)ccap, TPB), na);
+    }
     FSM_HIP(hipEventRecord(lg->ev, st));
     FSM_HIP(hipStreamWaitEvent(lg->cs, lg->ev, 0));
     {
@@ -4422,15 +4482,7 @@ void Miner::run() {
         if (fmap[x] >= 0) maxcount = std::max(maxcount, g->count[x]);
     W = (uint32_t)((maxcount + 31) / 32);
     pass_W = W;
-    // QP and pattern bitmap pools may take 40% of the free device memory
-    // (of the scratch arena's free bytes in an allocation-free call)
-    {
-        size_t fr = 0, tot = 0;
-        if (Arena* a = active_arena()) fr = a->free_bytes();
-        else FSM_HIP(hipMemGetInfo(&fr, &tot));
-        pool_budget = std::max<uint64_t>((uint64_t)(0.4 * (double)fr), (uint64_t)1 << 26);
-        if (opt.pool_budget_mib > 0) pool_budget = (uint64_t)opt.pool_budget_mib << 20;
-    }
+    refresh_pool_budget();
     lrank.alloc((size_t)g->n);
     {
         DBuf<unsigned> lcnt((size_t)G * F);

@@ -203,5 +203,5 @@ def test_tenth_scale_size5_matches_whole_oracle_result():
         say("cl1m at 1/10 scale: sizes 2..5")
         r = fsm.mine(g, gold["support"], gold["max_size"])
         assert r.patterns == want
-        learned = fsm.mine(g, gold["support"], gold["max_size"], force_overflow=True)
-        assert learned.patterns == want
+        forced = fsm.mine(g, gold["support"], gold["max_size"], force_overflow=True)
+        assert forced.patterns == want
