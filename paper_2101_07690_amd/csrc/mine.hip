@@ -206,10 +206,28 @@ __device__ __forceinline__ bool lex_less3(int32_t a0, int32_t a1, int32_t a2, in
 }
 
 // bit r of the bitmap at `bm`: read first, atomicOr only when unset
+// Device buffers live in global memory; reading them through pointers of
+// that address space lets the compiler use global (not flat) loads and
+// atomics, which do not hold up the LDS reads of the same wave.
+#define FSM_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ FSM_GLOBAL T* gmem(T* p) {
+    return (FSM_GLOBAL T*)p;
+}
+
+// Read-only for the whole kernel: a wave-uniform address loads through the
+// scalar unit into SGPRs.
+#define FSM_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const FSM_CONST T* cmem(const T* p) {
+    return (const FSM_CONST T*)p;
+}
+
 __device__ __forceinline__ void set_bit(uint32_t* bm, int32_t r) {
-    uint32_t* w = bm + (r >> 5);
-    uint32_t bit = 1u << (r & 31);
-    if (!(*w & bit)) atomicOr(w, bit);
+    FSM_GLOBAL uint32_t* w = gmem(bm) + (r >> 5);
+    const uint32_t bit = 1u << (r & 31);
+    if (!(*w & bit)) __hip_atomic_fetch_or(w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Domain passes cover the ranks in slices: rank r is set when it falls in
@@ -834,7 +852,7 @@ struct JoinArgs {
 };
 
 __device__ __forceinline__ bool f3_at(const uint8_t* f3, int F, int t, int a, int b, int c) {
-    return f3[((t * F + a) * F + b) * F + c] != 0;
+    return gmem(f3)[((t * F + a) * F + b) * F + c] != 0;
 }
 
 // Size-3 subgraphs (bit PIECE_*) that the piece slot (k; u, w) holds among
@@ -1565,7 +1583,7 @@ struct GroupBuild {
     int64_t nwork;
     uint64_t* kv;       // key, parent count
     uint64_t mask;
-    int32_t* wslot;     // group-table slot of each work item
+    uint32_t* wslot;    // group-table slot of each work item (tables up to 2^32 slots)
     unsigned* count;    // occupied slots
     uint32_t* flags;
     unsigned long long* kpar;   // work items per joining vertex
@@ -1583,7 +1601,7 @@ __global__ void k_group_insert(GroupBuild b) {
         const int32_t* row = b.par + p * (b.M + 1);
         const uint64_t key = group_key(row[i], row[b.M], i);
         int64_t s = ht_probe(b.kv, b.mask, key, true, b.count, b.flags, OVF_QP);
-        b.wslot[w] = (int32_t)s;
+        b.wslot[w] = (uint32_t)s;   // an overflowed attempt's slots are never read
         if (s >= 0) atomicAdd((unsigned long long*)&b.kv[2 * s + 1], 1ull);
         atomicAdd(&b.kpar[row[i]], 1ull);
     }
@@ -1633,7 +1651,7 @@ __global__ void k_key_tiles(const int32_t* gk, const int64_t* gcnt, const int64_
         tiles[g] = ((gcnt[g] + tile_p - 1) / tile_p) * ((npieces[gk[g]] + 63) / 64);
 }
 
-__global__ void k_group_fill(int64_t nwork, int M, const int32_t* wslot, const int64_t* gid,
+__global__ void k_group_fill(int64_t nwork, int M, const uint32_t* wslot, const int64_t* gid,
                              unsigned long long* cursor, int32_t* glist) {
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nwork;
          w += (int64_t)gridDim.x * blockDim.x) {
@@ -1711,23 +1729,30 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
     constexpr int M = N - 2;
     const int32_t u = cv[M], w = cv[M + 1];
     const uint32_t hu1 = nbr_hash(u), hu2 = nbr_hash2(u), hw1 = nbr_hash(w), hw2 = nbr_hash2(w);
-    int2 bu1[M], bu2[M], bw1[M], bw2[M];
+    // buckets read as 64-bit words (slot 0 low, slot 1 high)
+    uint64_t bu1[M], bu2[M], bw1[M], bw2[M];
+    const FSM_GLOBAL uint64_t* tab = gmem(reinterpret_cast<const uint64_t*>(H.tab));
+    const FSM_GLOBAL uint32_t* off = gmem(H.off);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        const uint32_t o = H.off[cv[j]], nb = H.off[cv[j] + 1] - o;
-        const int2 none = make_int2(-1, -1);
+        const uint32_t o = off[cv[j]], nb = off[cv[j] + 1] - o;
         const bool live = j != i && nb != 0;
         const uint32_t m = nb - 1;
-        bu1[j] = live ? H.tab[o + (hu1 & m)] : none;
-        bu2[j] = live ? H.tab[o + (hu2 & m)] : none;
-        bw1[j] = live ? H.tab[o + (hw1 & m)] : none;
-        bw2[j] = live ? H.tab[o + (hw2 & m)] : none;
+        bu1[j] = bu2[j] = bw1[j] = bw2[j] = ~0ull;
+        if (live) {
+            bu1[j] = tab[o + (hu1 & m)];
+            bu2[j] = tab[o + (hu2 & m)];
+            bw1[j] = tab[o + (hw1 & m)];
+            bw2[j] = tab[o + (hw2 & m)];
+        }
     }
+    const uint32_t uu = (uint32_t)u, ww = (uint32_t)w;
+    auto has = [](uint64_t b, uint32_t x) { return (uint32_t)b == x || (uint32_t)(b >> 32) == x; };
     uint32_t ec = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        if (in_bucket(bu1[j], u) || in_bucket(bu2[j], u)) ec |= 1u << (2 * j);
-        if (in_bucket(bw1[j], w) || in_bucket(bw2[j], w)) ec |= 1u << (2 * j + 1);
+        if (has(bu1[j], uu) || has(bu2[j], uu)) ec |= 1u << (2 * j);
+        if (has(bw1[j], ww) || has(bw2[j], ww)) ec |= 1u << (2 * j + 1);
     }
     return ec;
 }
@@ -1740,6 +1765,7 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
 template <int N, bool EXTRA>
 __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f3,
                                              const uint16_t* __restrict__ dtab,
+                                             const uint32_t* __restrict__ rb,
                                              const int32_t (&cv)[N],
                                              const int32_t (&lr)[N], int i, uint32_t types,
                                              uint32_t ec, uint64_t PA, uint64_t L, int32_t pslot,
@@ -1767,14 +1793,14 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
     for (int p = 0; p < M; ++p)
 #pragma unroll
         for (int q = p + 1; q < M; ++q)
-            if ((PA >> (8 * p + q)) & 1u) rpar |= rbit<N>(rk[p], rk[q]);
-    const uint32_t eku = rbit<N>(rki, rk[M]), ekw = rbit<N>(rki, rk[M + 1]);
-    const uint32_t euw = rbit<N>(rk[M], rk[M + 1]);
+            if ((PA >> (8 * p + q)) & 1u) rpar |= rb[rk[p] << 3 | rk[q]];
+    const uint32_t eku = rb[rki << 3 | rk[M]], ekw = rb[rki << 3 | rk[M + 1]];
+    const uint32_t euw = rb[rk[M] << 3 | rk[M + 1]];
     uint32_t cm[2 * M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-        cm[2 * j] = rbit<N>(rk[j], rk[M]);
-        cm[2 * j + 1] = rbit<N>(rk[j], rk[M + 1]);
+        cm[2 * j] = rb[rk[j] << 3 | rk[M]];
+        cm[2 * j + 1] = rb[rk[j] << 3 | rk[M + 1]];
     }
     const uint32_t want =
         ((1u << rki) | (1u << rk[M]) | (1u << rk[M + 1])) | ((uint32_t)rki << 8);
@@ -1890,14 +1916,19 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
 template <int N, bool EXTRA>
 __device__ __forceinline__ void join_tiles(const TileArgs& a) {
     constexpr int M = N - 2;
-    // sizes 4 and 5: the dissection table (2^(n(n-1)/2) entries, at most
-    // 2 KB) is read from LDS
+    // LDS tables: for sizes 4 and 5 the dissection table (2^(n(n-1)/2)
+    // entries, at most 2 KB); for every size the bit of the vertex pair with
+    // id ranks (x, y) in the child's rank-order adjacency, srb[x * 8 + y]
     constexpr int DT_LDS = N <= 5 ? 1 << (N * (N - 1) / 2) : 1;
     __shared__ uint16_t sdt[DT_LDS];
-    if (N <= 5) {
+    __shared__ uint32_t srb[64];
+    if (N <= 5)
         for (int x = threadIdx.x; x < DT_LDS; x += TPB) sdt[x] = a.dtab[x];
-        __syncthreads();
+    if (threadIdx.x < 64) {
+        const int x = threadIdx.x >> 3, y = threadIdx.x & 7;
+        srb[threadIdx.x] = (x < N && y < N && x != y) ? rbit<N>(x, y) : 0u;
     }
+    __syncthreads();
     const uint16_t* __restrict__ dtab = N <= 5 ? sdt : a.dtab;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (TPB / 64);
@@ -1909,36 +1940,42 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
         if (a.queue) {
             unsigned long long nt = 0;
             if (lane == 0) nt = atomicAdd(&a.ctr[2], 1ull);
-            t = (int64_t)__shfl(nt, 0, 64);
+            // the tile index is wave-uniform: keep it (and all that derives
+            // from it: group, parent rows, their labels) in scalar registers
+            nt = __shfl(nt, 0, 64);
+            t = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(nt >> 32)) << 32) |
+                          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)nt));
         } else {
             t += nw;
         }
         if (t >= a.ntiles) break;
         // an overflowed pass is rerun with a larger table: stop early
-        if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & OVF_QP)
+        if (__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & OVF_QP)
             break;
         // group of tile t: last g with toff[g] <= t (t only grows: gallop)
+        const auto toff = cmem(a.toff);
         {
             int64_t step = 1;
-            while (g + step < a.ngroups && a.toff[g + step] <= t) { g += step; step <<= 1; }
+            while (g + step < a.ngroups && toff[g + step] <= t) { g += step; step <<= 1; }
             int64_t lo = g, hi = min(g + step, a.ngroups - 1);
             while (lo < hi) {
                 int64_t mid = (lo + hi + 1) >> 1;
-                if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+                if (toff[mid] <= t) lo = mid; else hi = mid - 1;
             }
             g = lo;
         }
-        const int32_t k = a.gk[g];
-        const int64_t Q = a.npieces[k];
+        const int32_t k = cmem(a.gk)[g];
+        const int64_t Q = cmem(a.npieces)[k];
         const int64_t nqt = (Q + 63) / 64;
-        const int64_t local = t - a.toff[g];
+        const int64_t local = t - toff[g];
         const int64_t pt = local / nqt, qt = local - pt * nqt;
         const int64_t q = qt * 64 + lane;
-        const int32_t rk = a.row[k];
-        const int32_t dk = a.row[k + 1] - rk;
+        const int32_t rk = cmem(a.row)[k];
+        const int32_t dk = cmem(a.row)[k + 1] - rk;
         const int64_t ncen = (int64_t)dk * (dk - 1) / 2;
-        const int lk = (int)(a.vinfo[k] >> 26);
-        const uint64_t gid = (uint64_t)a.vg[k];
+        const int lk = (int)(cmem(a.vinfo)[k] >> 26);
+        const uint64_t gid = (uint64_t)cmem(a.vg)[k];
         const uint8_t* f3 = a.f3 + (size_t)gid * 2 * a.F * a.F * a.F;
         // this lane's piece
         int32_t u = -1, w = -1, lru = 0, lrw = 0;
@@ -1980,17 +2017,17 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
         int32_t q0 = 0, q1 = 0, q2 = 0;
         if (N == 5 && !a.pkey) sort3(k, u, w, q0, q1, q2);
         // sorted lists: the tile's smallest key (every lane's key is >= it)
-        const uint64_t tkey = (N == 5 && a.pkey) ? a.pkey[a.poff[k] + qt * 64] : 0;
+        const uint64_t tkey = (N == 5 && a.pkey) ? cmem(a.pkey)[cmem(a.poff)[k] + qt * 64] : 0;
         // parent range of the tile in glist (work items can exceed 2^31)
-        const int64_t pb = a.goff[g] + pt * a.tile_p;
-        const int64_t pe = min(a.goff[g] + a.gcnt[g], pb + a.tile_p);
+        const int64_t pb = cmem(a.goff)[g] + pt * a.tile_p;
+        const int64_t pe = min(cmem(a.goff)[g] + cmem(a.gcnt)[g], pb + a.tile_p);
         if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
         // no lane holds a piece the join may take (infrequent or unsampled):
         // the tile has no children
         if (__ballot(types != 0) == 0ull) continue;
         c.b0 = c.b1 = 0;
         for (int64_t pp = pb; pp < pe; ++pp) {
-            const int32_t* prow = a.par + (int64_t)a.glist[pp] * (M + 1);
+            const FSM_CONST int32_t* prow = cmem(a.par) + (int64_t)cmem(a.glist)[pp] * (M + 1);
             int32_t cv[N], lr[N];
             int i = 0;
             int32_t mu = INT_MAX;
@@ -2002,7 +2039,7 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
             }
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const uint32_t vi = a.vinfo[cv[j]];
+                const uint32_t vi = cmem(a.vinfo)[cv[j]];
                 lr[j] = (int32_t)(vi & RANK_MASK);
                 L |= (uint64_t)(vi >> 26) << (6 * j);
                 if (j != i) mu = min(mu, cv[j]);
@@ -2042,7 +2079,7 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
             if (EXTRA && ok && a.item_thr && hsh >= a.item_thr[(int64_t)pslot * M + i]) ok = false;
             int got = 0;
             if (ok) {
-                const uint64_t PA = a.padj[pslot];
+                const uint64_t PA = cmem(a.padj)[pslot];
                 cv[M] = u;
                 cv[M + 1] = w;
                 const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
@@ -2054,8 +2091,8 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
                     L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
                 lr[M] = lru;
                 lr[M + 1] = lrw;
-                got = children_tile<N, EXTRA>(a, f3, dtab, cv, lr, i, ty, ec, PA, Lc, pslot, lu, lw,
-                                              c);
+                got = children_tile<N, EXTRA>(a, f3, dtab, srb, cv, lr, i, ty, ec, PA, Lc, pslot,
+                                              lu, lw, c);
                 emit += (unsigned long long)got;
                 bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
             }
@@ -3148,6 +3185,7 @@ struct Miner {
     DBuf<uint32_t> pool, ppool;     // QP-position bitmaps, pattern-orbit bitmaps
     uint64_t pool_words = 0, ppool_words = 0;
     uint64_t pool_budget = 0;     // bytes for the QP and pattern bitmap pools
+    uint64_t released_pool_bytes = 0;   // pools released by the last level
     uint32_t pass_W = 0;          // current domain pass: words per bitmap,
     int32_t pass_rbase = 0;       // first rank of its slice,
     const int32_t* pass_porb = nullptr;        // its candidate bitmap map,
@@ -3190,11 +3228,16 @@ struct Miner {
     // memory free now (of the scratch arena's free bytes in an
     // allocation-free call), counting the pools just released, which a
     // caching allocator may keep.
-    void refresh_pool_budget() {
-        const uint64_t released = (pool_words + ppool_words) * sizeof(uint32_t);
+    void release_pools() {
+        released_pool_bytes = (pool_words + ppool_words) * sizeof(uint32_t);
         pool.reset();
         ppool.reset();
         pool_words = ppool_words = 0;
+    }
+    void refresh_pool_budget() {
+        const uint64_t held = (pool_words + ppool_words) * sizeof(uint32_t);
+        release_pools();
+        const uint64_t released = std::max(held, released_pool_bytes);
         size_t fr = 0, tot = 0;
         if (Arena* a = active_arena()) fr = a->free_bytes();
         else FSM_HIP(hipMemGetInfo(&fr, &tot));
@@ -3507,6 +3550,7 @@ struct Miner {
             if (hs[i] >= tg[graph_of(hk[i], L.n)]) L.freq.emplace_back(hk[i], hs[i]);
         std::sort(L.freq.begin(), L.freq.end());
         L.st.frequent = (int64_t)L.freq.size();
+        release_pools();
     }
 
     // count / scan / fill of the frequent embeddings of level L
@@ -3660,6 +3704,7 @@ bool Miner::captured_level(Level& L, MakeArgs&& make_args) {
         if (hs[i] >= tg[graph_of(hk[i], n)]) L.freq.emplace_back(hk[i], hs[i]);
     std::sort(L.freq.begin(), L.freq.end());
     L.st.frequent = (int64_t)L.freq.size();
+    release_pools();
     ++captured;
     return true;
 }
@@ -3864,8 +3909,9 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
         fail(FSM_EUNSUPPORTED, "more than 2^31-1 parent embeddings");
     G.pieces = pieces ? pieces : npieces.p;
     const int64_t n = g->n;
-    uint64_t cap = pow2_at_least((uint64_t)std::min<int64_t>(nwork, n * 16) * 2 + 16);
-    DBuf<int32_t> wslot((size_t)nwork);
+    uint64_t cap = std::min<uint64_t>(
+        pow2_at_least((uint64_t)std::min<int64_t>(nwork, n * 16) * 2 + 16), 1ull << 32);
+    DBuf<uint32_t> wslot((size_t)nwork);
     DBuf<uint64_t> kv;
     DBuf<unsigned> cnt(1);
     DBuf<unsigned long long> kpar((size_t)n);
@@ -3881,7 +3927,10 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
         k_group_insert<<<grid_for(nwork, TPB), TPB, 0, st>>>(b);
         FSM_LAUNCH_CHECK();
         if (!(scalar_to_host(flags.p) & OVF_QP)) break;
-        if (attempt >= 6) fail(FSM_EOVERFLOW, "join grouping table overflow");
+        // slots are stored as 32-bit words
+        if (attempt >= 6 || cap * 4 > (1ull << 32))
+            fail(FSM_EOVERFLOW, "join grouping table overflow (%llu slots)",
+                 (unsigned long long)cap);
         cap *= 4;
     }
     // parent range of every key, then each sub-group's run inside it
