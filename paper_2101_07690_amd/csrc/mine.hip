@@ -60,6 +60,9 @@ constexpr uint64_t VALID = 1ull << 63;
 constexpr uint64_t FREQ = 1ull << 62;
 constexpr uint64_t REGION_MASK = (1ull << 41) - 1;
 constexpr int JOIN_CHUNK = 4;   // work items fetched per queue access
+// buckets of one vertex's neighbour table: the join addresses a bucket by a
+// 32-bit byte offset from the table's base
+constexpr int64_t NB_MAX = 1ll << 29;
 
 enum : uint32_t { OVF_QP = 1, OVF_CODE = 2, ERR_MISSING = 8, ERR_FILL = 16, ERR_BATCH = 32,
                   ERR_GRAPH = 64 };
@@ -291,17 +294,19 @@ __host__ __device__ __forceinline__ uint32_t nbr_hash2(int32_t x) {
     return h ^ (h >> 13);
 }
 
-__device__ __forceinline__ bool in_bucket(int2 b, int32_t x) { return b.x == x || b.y == x; }
-
 // b's table holds x (nb = its bucket count, o its first bucket)
 __device__ __forceinline__ bool nbr_has(const int2* tab, uint32_t o, uint32_t nb, int32_t x) {
-    const int2 p = tab[o + (nbr_hash(x) & (nb - 1))];
-    const int2 q = tab[o + (nbr_hash2(x) & (nb - 1))];
-    return in_bucket(p, x) || in_bucket(q, x);
+    // a bucket read as one 64-bit word (slot 0 low, slot 1 high)
+    const FSM_GLOBAL uint64_t* t = gmem(reinterpret_cast<const uint64_t*>(tab)) + o;
+    const uint64_t p = t[nbr_hash(x) & (nb - 1)];
+    const uint64_t q = t[nbr_hash2(x) & (nb - 1)];
+    const uint32_t y = (uint32_t)x;
+    return (uint32_t)p == y || (uint32_t)(p >> 32) == y || (uint32_t)q == y ||
+           (uint32_t)(q >> 32) == y;
 }
 
 __device__ __forceinline__ bool has_edge(const NbrHash& H, int32_t b, int32_t x) {
-    const uint32_t o = H.off[b], nb = H.off[b + 1] - o;
+    const uint32_t o = gmem(H.off)[b], nb = gmem(H.off)[b + 1] - o;
     return nb != 0 && nbr_has(H.tab, o, nb, x);
 }
 
@@ -400,7 +405,8 @@ __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t*
 // neighbour-table sizes: pow2 >= 2*deg, 0 for isolated vertices
 // Buckets of each vertex's neighbour table: the smallest power of two >=
 // deg (two slots each), times 2^grow[v] after failed builds.
-__global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, int64_t* nb) {
+__global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, int64_t* nb,
+                            unsigned* big) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = row[v + 1] - row[v];
@@ -410,6 +416,7 @@ __global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, 
             while (c < d) c <<= 1;
             c <<= grow[v];
         }
+        if (c > NB_MAX) atomicOr(big, 1u);
         nb[v] = c;
     }
 }
@@ -1732,18 +1739,25 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
     // buckets read as 64-bit words (slot 0 low, slot 1 high)
     uint64_t bu1[M], bu2[M], bw1[M], bw2[M];
     const FSM_GLOBAL uint64_t* tab = gmem(reinterpret_cast<const uint64_t*>(H.tab));
-    const FSM_GLOBAL uint32_t* off = gmem(H.off);
+    const FSM_CONST uint32_t* off = cmem(H.off);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
+        // cv[j] is wave-uniform: its table's base and size sit in scalar
+        // registers, and a bucket is a 32-bit byte offset from that base
+        // (at most 2^29 buckets per vertex, checked when the tables are built)
         const uint32_t o = off[cv[j]], nb = off[cv[j] + 1] - o;
         const bool live = j != i && nb != 0;
         const uint32_t m = nb - 1;
+        const FSM_GLOBAL char* base = reinterpret_cast<const FSM_GLOBAL char*>(tab + o);
+        auto bucket = [&](uint32_t h) {
+            return *reinterpret_cast<const FSM_GLOBAL uint64_t*>(base + ((h & m) << 3));
+        };
         bu1[j] = bu2[j] = bw1[j] = bw2[j] = ~0ull;
         if (live) {
-            bu1[j] = tab[o + (hu1 & m)];
-            bu2[j] = tab[o + (hu2 & m)];
-            bw1[j] = tab[o + (hw1 & m)];
-            bw2[j] = tab[o + (hw2 & m)];
+            bu1[j] = bucket(hu1);
+            bu2[j] = bucket(hu2);
+            bw1[j] = bucket(hw1);
+            bw2[j] = bucket(hw2);
         }
     }
     const uint32_t uu = (uint32_t)u, ww = (uint32_t)w;
@@ -1909,10 +1923,13 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
     return got;
 }
 
-// At most 128 VGPRs (4 waves per SIMD): the occupancy hides the latency of
-// the adjacency probes and bitmap reads better than the extra registers.
-// EXTRA = false builds the exact edge-induced join without the sampling and
-// vertex-induced paths (fewer live registers).
+// Occupancy hides the latency of the adjacency probes and bitmap reads
+// better than extra registers would (the kernel entry below sets the waves
+// per SIMD).  Wave-uniform values (the tile's group, the parent row, its
+// labels, ranks and adjacency) live in scalar registers: their loads go
+// through the constant address space.  EXTRA = false builds the exact
+// edge-induced join without the sampling and vertex-induced paths (fewer
+// live registers).
 template <int N, bool EXTRA>
 __device__ __forceinline__ void join_tiles(const TileArgs& a) {
     constexpr int M = N - 2;
@@ -2124,9 +2141,11 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
 // The domain pass takes its arguments from device memory: the fields are
 // read where they are used instead of being held (and spilled) in scalar
 // registers for the whole kernel.
+// Five waves per SIMD for the plain pass (96 VGPRs, a few spills outside
+// the inner loop); the sampled / vertex-induced build keeps four.
 template <int N, bool EXTRA>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_join_tiles_p(
-    const TileArgs* __restrict__ a) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(EXTRA ? 4 : 5, 8))) void
+k_join_tiles_p(const TileArgs* __restrict__ a) {
     join_tiles<N, EXTRA>(*a);
 }
 
@@ -2168,7 +2187,8 @@ struct SingleTileArgs {
 
 template <int N>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_single_tiles(
-    SingleTileArgs a) {
+    const SingleTileArgs* __restrict__ ap) {
+    const SingleTileArgs& a = *ap;
     constexpr int M = N - 1;
     const int lane = threadIdx.x & 63;
     unsigned long long emit = 0, cands = 0, bytes = 0;
@@ -2177,25 +2197,31 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     for (;;) {
         unsigned long long nt = 0;
         if (lane == 0) nt = atomicAdd(&a.ctr[2], 1ull);
-        const int64_t t = (int64_t)__shfl(nt, 0, 64);
+        // wave-uniform tile index: the group's fields load into scalar registers
+        nt = __shfl(nt, 0, 64);
+        const int64_t t =
+            (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(nt >> 32)) << 32) |
+                      (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)nt));
         if (t >= a.ntiles) break;
-        if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & OVF_QP)
+        if (__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & OVF_QP)
             break;
+        const auto toff = cmem(a.toff);
         {   // group of tile t (t only grows: gallop)
             int64_t step = 1;
-            while (g + step < a.ngroups && a.toff[g + step] <= t) { g += step; step <<= 1; }
+            while (g + step < a.ngroups && toff[g + step] <= t) { g += step; step <<= 1; }
             int64_t lo = g, hi = min(g + step, a.ngroups - 1);
             while (lo < hi) {
                 int64_t mid = (lo + hi + 1) >> 1;
-                if (a.toff[mid] <= t) lo = mid; else hi = mid - 1;
+                if (toff[mid] <= t) lo = mid; else hi = mid - 1;
             }
             g = lo;
         }
-        const int32_t k = a.gk[g];
-        const int32_t rk = a.row[k];
-        const int64_t Q = a.row[k + 1] - rk;
+        const int32_t k = cmem(a.gk)[g];
+        const int32_t rk = cmem(a.row)[k];
+        const int64_t Q = cmem(a.row)[k + 1] - rk;
         const int64_t nqt = (Q + 63) / 64;
-        const int64_t local = t - a.toff[g];
+        const int64_t local = t - toff[g];
         const int64_t pt = local / nqt, qt = local - pt * nqt;
         // short neighbour lists (<= 32) pack 64 / D parents per step into
         // the wave, D = the list length rounded up to a power of two
@@ -2219,14 +2245,14 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             lru = (int32_t)(iu & RANK_MASK);
         }
         // parent range of the tile in glist (work items can exceed 2^31)
-        const int64_t pb = a.goff[g] + pt * a.tile_p;
-        const int64_t pe = min(a.goff[g] + a.gcnt[g], pb + a.tile_p);
+        const int64_t pb = cmem(a.goff)[g] + pt * a.tile_p;
+        const int64_t pe = min(cmem(a.goff)[g] + cmem(a.gcnt)[g], pb + a.tile_p);
         if (lane == 0) cands += (unsigned long long)((int64_t)(pe - pb) * min((int64_t)64, Q - qt * 64));
         if (__ballot(live) == 0ull) continue;
         c.b0 = c.b1 = 0;
-        const uint64_t gid = (uint64_t)a.vg[k];
+        const uint64_t gid = (uint64_t)cmem(a.vg)[k];
         for (int64_t pp = pb + sub0; pp < pe; pp += step) {
-            const int32_t* prow = a.par + (int64_t)a.glist[pp] * (M + 1);
+            const FSM_GLOBAL int32_t* prow = gmem(a.par) + (int64_t)gmem(a.glist)[pp] * (M + 1);
             int32_t cv[N], lr[N];
             int i = 0;
             uint64_t L = 0;
@@ -2237,7 +2263,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             }
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                const uint32_t vi = a.vinfo[cv[j]];
+                const uint32_t vi = gmem(a.vinfo)[cv[j]];
                 lr[j] = (int32_t)(vi & RANK_MASK);
                 L |= (uint64_t)(vi >> 26) << (6 * j);
             }
@@ -2248,7 +2274,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             for (int j = 0; j < M; ++j) ok = ok && cv[j] != u;
             int got = 0;
             if (ok) {
-                const uint64_t PA = a.padj[pslot];
+                const uint64_t PA = gmem(a.padj)[pslot];
                 uint32_t ec = 0;
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
@@ -3196,6 +3222,8 @@ struct Miner {
     Rec hrec{};
     DBuf<TileArgs> dtile;   // device copy of the domain pass's arguments
     TileArgs htile{};
+    DBuf<SingleTileArgs> dstile;   // the same for the single-vertex domain pass
+    SingleTileArgs hstile{};
     DBuf<unsigned long long> counters;   // [emitted, candidates, work queue, bytes]
     DBuf<uint32_t> flags;
     uint32_t W = 1;
@@ -3771,14 +3799,18 @@ void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32
     const int64_t n = g->n;
     DBuf<int64_t> nb((size_t)n + 1);
     DBuf<uint8_t> grow((size_t)n), failed((size_t)n);
-    DBuf<unsigned> nfailed(1);
+    DBuf<unsigned> nfailed(1), big(1);
     grow.zero();
     for (int attempt = 0;; ++attempt) {
-        k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(row, n, grow.p, nb.p);
+        big.zero();
+        k_nbr_sizes<<<grid_for(n, TPB), TPB, 0, st>>>(row, n, grow.p, nb.p, big.p);
         FSM_LAUNCH_CHECK();
         const int64_t total = scan_exclusive(nb.p, nb.p, n);
         if (total >= (int64_t)UINT32_MAX)
             fail(FSM_EUNSUPPORTED, "neighbour tables exceed 2^32 buckets");
+        if (scalar_to_host(big.p))
+            fail(FSM_EUNSUPPORTED, "a vertex's neighbour table exceeds %lld buckets",
+                 (long long)NB_MAX);
         off.alloc((size_t)n + 1);
         tab.alloc((size_t)(total > 0 ? total : 1));
         failed.zero();
@@ -4427,7 +4459,12 @@ void Miner::join_single(int n) {
             if (pass == 0) join_total = 0.f;
             jt.start();
             if (G.ntiles > 0) {
-                const SingleTileArgs t = tile_args(R);
+                // arguments from device memory: as kernel arguments they
+                // would take scalar registers the loop needs
+                hstile = tile_args(R);
+                FSM_HIP(hipMemcpyAsync(dstile.p, &hstile, sizeof(SingleTileArgs),
+                                       hipMemcpyHostToDevice, st));
+                const SingleTileArgs* t = dstile.p;
                 switch (n) {
                     case 3: k_single_tiles<3><<<grid_persistent, TPB, 0, st>>>(t); break;
                     case 4: k_single_tiles<4><<<grid_persistent, TPB, 0, st>>>(t); break;
@@ -4546,6 +4583,7 @@ void Miner::run() {
     FSM_LAUNCH_CHECK();
     drec.alloc(1);
     dtile.alloc(1);
+    dstile.alloc(1);
     counters.alloc(4);
     flags.alloc(1);
 
