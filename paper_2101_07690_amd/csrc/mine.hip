@@ -1729,44 +1729,59 @@ struct LaneCache {
 // Adjacency of every parent vertex except k with the piece's two new
 // vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  The parent vertex
 // is the same across the wave, so all lanes read the same small table; each
-// test is two bucket reads, all issued before any is compared.
+// test is two bucket reads, all issued before any is compared.  Only the
+// M - 1 positions other than i are probed (position j of the jj-th probe is
+// jj, or jj + 1 past i; wave-uniform).  A bucket's byte offset is the
+// lane's pre-shifted hash masked by the table's (bucket count - 1) << 3.
+// Connecting edges are rare: the bits are assembled only when some lane of
+// the wave has one.
 template <int N>
 __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int32_t (&cv)[N],
                                                      int i) {
     constexpr int M = N - 2;
     const int32_t u = cv[M], w = cv[M + 1];
-    const uint32_t hu1 = nbr_hash(u), hu2 = nbr_hash2(u), hw1 = nbr_hash(w), hw2 = nbr_hash2(w);
-    // buckets read as 64-bit words (slot 0 low, slot 1 high)
-    uint64_t bu1[M], bu2[M], bw1[M], bw2[M];
+    const uint32_t su1 = nbr_hash(u) << 3, su2 = nbr_hash2(u) << 3;
+    const uint32_t sw1 = nbr_hash(w) << 3, sw2 = nbr_hash2(w) << 3;
     const FSM_GLOBAL uint64_t* tab = gmem(reinterpret_cast<const uint64_t*>(H.tab));
     const FSM_CONST uint32_t* off = cmem(H.off);
+    uint64_t bu1[M - 1], bu2[M - 1], bw1[M - 1], bw2[M - 1];
+    bool live[M - 1];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
+    for (int jj = 0; jj < M - 1; ++jj) {
+        const int32_t b = jj < i ? cv[jj] : cv[jj + 1];
         // cv[j] is wave-uniform: its table's base and size sit in scalar
-        // registers, and a bucket is a 32-bit byte offset from that base
-        // (at most 2^29 buckets per vertex, checked when the tables are built)
-        const uint32_t o = off[cv[j]], nb = off[cv[j] + 1] - o;
-        const bool live = j != i && nb != 0;
-        const uint32_t m = nb - 1;
-        const FSM_GLOBAL char* base = reinterpret_cast<const FSM_GLOBAL char*>(tab + o);
-        auto bucket = [&](uint32_t h) {
-            return *reinterpret_cast<const FSM_GLOBAL uint64_t*>(base + ((h & m) << 3));
+        // registers (at most 2^29 buckets per vertex, checked when the
+        // tables are built).  A vertex without a table reads bucket 0 of
+        // the whole array (it exists) and its result is dropped.
+        const uint32_t o = off[b], nb = off[b + 1] - o;
+        live[jj] = nb != 0;
+        const uint32_t m8 = nb ? (nb - 1) << 3 : 0u;
+        const FSM_GLOBAL char* base = reinterpret_cast<const FSM_GLOBAL char*>(tab + (nb ? o : 0u));
+        auto bucket = [&](uint32_t sh) {
+            return *reinterpret_cast<const FSM_GLOBAL uint64_t*>(base + (sh & m8));
         };
-        bu1[j] = bu2[j] = bw1[j] = bw2[j] = ~0ull;
-        if (live) {
-            bu1[j] = bucket(hu1);
-            bu2[j] = bucket(hu2);
-            bw1[j] = bucket(hw1);
-            bw2[j] = bucket(hw2);
-        }
+        bu1[jj] = bucket(su1);
+        bu2[jj] = bucket(su2);
+        bw1[jj] = bucket(sw1);
+        bw2[jj] = bucket(sw2);
     }
     const uint32_t uu = (uint32_t)u, ww = (uint32_t)w;
-    auto has = [](uint64_t b, uint32_t x) { return (uint32_t)b == x || (uint32_t)(b >> 32) == x; };
+    auto has = [](uint64_t x, uint32_t y) { return (uint32_t)x == y || (uint32_t)(x >> 32) == y; };
+    bool mu[M - 1], mw[M - 1];
+    bool any = false;
+#pragma unroll
+    for (int jj = 0; jj < M - 1; ++jj) {
+        mu[jj] = live[jj] && (has(bu1[jj], uu) || has(bu2[jj], uu));
+        mw[jj] = live[jj] && (has(bw1[jj], ww) || has(bw2[jj], ww));
+        any = any || mu[jj] || mw[jj];
+    }
+    if (__ballot(any) == 0ull) return 0u;
     uint32_t ec = 0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        if (has(bu1[j], uu) || has(bu2[j], uu)) ec |= 1u << (2 * j);
-        if (has(bw1[j], ww) || has(bw2[j], ww)) ec |= 1u << (2 * j + 1);
+    for (int jj = 0; jj < M - 1; ++jj) {
+        const int j = jj < i ? jj : jj + 1;
+        if (mu[jj]) ec |= 1u << (2 * j);
+        if (mw[jj]) ec |= 2u << (2 * j);
     }
     return ec;
 }

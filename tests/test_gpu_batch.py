@@ -1,6 +1,10 @@
 """GPU parity of batched mining (many graphs in one pass): each graph's
 result must equal the oracle's, and equal what the plain per-graph call
 returns."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -9,6 +13,7 @@ import paper_2101_07690_amd as fsm
 import synth
 
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def build(src, dst, lab):
@@ -57,6 +62,38 @@ def test_full_batch_equals_plain_calls():
         for i in range(0, len(ws), 8):
             plain = fsm.mine(gs[i], ws[i]["support"], 5)
             assert res[i].patterns == plain.patterns, i
+    finally:
+        for g in gs:
+            g.close()
+
+
+def batch_digest(patterns):
+    # the serialisation of tests/golden/make_batch_digests.py: one line per
+    # pattern, "size labels(comma-separated) adjacency support", in order
+    h = hashlib.sha256()
+    for size, labels, adj, sup in patterns:
+        h.update(f"{size} {','.join(str(x) for x in labels)} {adj} {sup}\n".encode())
+    return h.hexdigest()
+
+
+def test_batch256_every_graph_matches_oracle_digest():
+    """All 256 graphs of the batch workload mined batched (sizes <= 5,
+    t_g = 2% of n_g) against the oracle's per-graph pattern count and result
+    digest (tests/golden/batch256_oracle_digests.json)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "batch256_oracle_digests.json")))
+    ws = synth.batch_workload()
+    assert len(gold["graphs"]) == len(ws)
+    for w, e in zip(ws, gold["graphs"]):
+        assert e["graph_sha256"] == synth.graph_sha256(w["src"], w["dst"], w["vertex_labels"])
+    gs = [build(w["src"], w["dst"], w["vertex_labels"]) for w in ws]
+    try:
+        print("batch256: mining every graph batched", flush=True)
+        res = fsm.mine_batch(gs, [w["support"] for w in ws], gold["max_size"])
+        bad = [i for i, (r, e) in enumerate(zip(res, gold["graphs"]))
+               if len(r) != e["patterns"] or batch_digest(r.patterns) != e["digest"]]
+        print(f"batch256: {sum(len(r) for r in res)} patterns, {len(bad)} graphs differ",
+              flush=True)
+        assert not bad, bad[:10]
     finally:
         for g in gs:
             g.close()
