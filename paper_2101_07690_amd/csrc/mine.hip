@@ -1729,23 +1729,27 @@ struct LaneCache {
 // Adjacency of every parent vertex except k with the piece's two new
 // vertices: bit 2j (2j+1) = parent position j ~ u (~ w).  The parent vertex
 // is the same across the wave, so all lanes read the same small table; each
-// test is two bucket reads, all issued before any is compared.  Only the
-// M - 1 positions other than i are probed (position j of the jj-th probe is
-// jj, or jj + 1 past i; wave-uniform).  A bucket's byte offset is the
-// lane's pre-shifted hash masked by the table's (bucket count - 1) << 3.
-// Connecting edges are rare: the bits are assembled only when some lane of
-// the wave has one.
+// test is two bucket reads.  Only the M - 1 positions other than i are
+// probed (position j of the jj-th probe is jj, or jj + 1 past i;
+// wave-uniform).  A bucket's byte offset is the lane's pre-shifted hash
+// masked by the table's (bucket count - 1) << 3.  The reads are issued
+// first (probe_issue) and compared later (probe_bits), so that work not
+// depending on them can cover their latency.
 template <int N>
-__device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int32_t (&cv)[N],
-                                                     int i) {
+struct Probe {
+    uint64_t bu1[N - 3], bu2[N - 3], bw1[N - 3], bw2[N - 3];
+    bool live[N - 3];
+};
+
+template <int N>
+__device__ __forceinline__ Probe<N> probe_issue(const NbrHash& H, const int32_t (&cv)[N], int i) {
     constexpr int M = N - 2;
     const int32_t u = cv[M], w = cv[M + 1];
     const uint32_t su1 = nbr_hash(u) << 3, su2 = nbr_hash2(u) << 3;
     const uint32_t sw1 = nbr_hash(w) << 3, sw2 = nbr_hash2(w) << 3;
     const FSM_GLOBAL uint64_t* tab = gmem(reinterpret_cast<const uint64_t*>(H.tab));
     const FSM_CONST uint32_t* off = cmem(H.off);
-    uint64_t bu1[M - 1], bu2[M - 1], bw1[M - 1], bw2[M - 1];
-    bool live[M - 1];
+    Probe<N> P;
 #pragma unroll
     for (int jj = 0; jj < M - 1; ++jj) {
         const int32_t b = jj < i ? cv[jj] : cv[jj + 1];
@@ -1754,25 +1758,33 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
         // tables are built).  A vertex without a table reads bucket 0 of
         // the whole array (it exists) and its result is dropped.
         const uint32_t o = off[b], nb = off[b + 1] - o;
-        live[jj] = nb != 0;
+        P.live[jj] = nb != 0;
         const uint32_t m8 = nb ? (nb - 1) << 3 : 0u;
         const FSM_GLOBAL char* base = reinterpret_cast<const FSM_GLOBAL char*>(tab + (nb ? o : 0u));
         auto bucket = [&](uint32_t sh) {
             return *reinterpret_cast<const FSM_GLOBAL uint64_t*>(base + (sh & m8));
         };
-        bu1[jj] = bucket(su1);
-        bu2[jj] = bucket(su2);
-        bw1[jj] = bucket(sw1);
-        bw2[jj] = bucket(sw2);
+        P.bu1[jj] = bucket(su1);
+        P.bu2[jj] = bucket(su2);
+        P.bw1[jj] = bucket(sw1);
+        P.bw2[jj] = bucket(sw2);
     }
-    const uint32_t uu = (uint32_t)u, ww = (uint32_t)w;
+    return P;
+}
+
+// The connecting-edge bits of an issued probe.  Connecting edges are rare:
+// the bits are assembled only when some lane of the wave has one.
+template <int N>
+__device__ __forceinline__ uint32_t probe_bits(const Probe<N>& P, const int32_t (&cv)[N], int i) {
+    constexpr int M = N - 2;
+    const uint32_t uu = (uint32_t)cv[M], ww = (uint32_t)cv[M + 1];
     auto has = [](uint64_t x, uint32_t y) { return (uint32_t)x == y || (uint32_t)(x >> 32) == y; };
     bool mu[M - 1], mw[M - 1];
     bool any = false;
 #pragma unroll
     for (int jj = 0; jj < M - 1; ++jj) {
-        mu[jj] = live[jj] && (has(bu1[jj], uu) || has(bu2[jj], uu));
-        mw[jj] = live[jj] && (has(bw1[jj], ww) || has(bw2[jj], ww));
+        mu[jj] = P.live[jj] && (has(P.bu1[jj], uu) || has(P.bu2[jj], uu));
+        mw[jj] = P.live[jj] && (has(P.bw1[jj], ww) || has(P.bw2[jj], ww));
         any = any || mu[jj] || mw[jj];
     }
     if (__ballot(any) == 0ull) return 0u;
@@ -1786,6 +1798,12 @@ __device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int
     return ec;
 }
 
+template <int N>
+__device__ __forceinline__ uint32_t connecting_edges(const NbrHash& H, const int32_t (&cv)[N],
+                                                     int i) {
+    return probe_bits<N>(probe_issue<N>(H, cv, i), cv, i);
+}
+
 // All children of one (parent, position, piece) candidate in the domain
 // pass.  The dissection check is a lookup in a table indexed by the child's
 // adjacency with vertices in id order (the rule depends on nothing else);
@@ -1797,8 +1815,8 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                                              const uint32_t* __restrict__ rb,
                                              const int32_t (&cv)[N],
                                              const int32_t (&lr)[N], int i, uint32_t types,
-                                             uint32_t ec, uint64_t PA, uint64_t L, int32_t pslot,
-                                             int lu, int lw, LaneCache& c) {
+                                             const Probe<N>& pr, uint64_t PA, uint64_t L,
+                                             int32_t pslot, int lu, int lw, LaneCache& c) {
     constexpr int M = N - 2;
     // rank of every vertex by id: the vertices are distinct, so one compare
     // per pair decides both ranks
@@ -1833,6 +1851,8 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
     }
     const uint32_t want =
         ((1u << rki) | (1u << rk[M]) | (1u << rk[M + 1])) | ((uint32_t)rki << 8);
+    // the adjacency reads were issued before the work above
+    const uint32_t ec = probe_bits<N>(pr, cv, i);
     // connecting edges allowed by the pruning: pieces joined to k by both
     // new vertices (k-centre wedge, triangle) and k-leaf wedges
     uint32_t allow_both = ec, allow_kl = ec;
@@ -2114,7 +2134,7 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
                 const uint64_t PA = cmem(a.padj)[pslot];
                 cv[M] = u;
                 cv[M + 1] = w;
-                const uint32_t ec = connecting_edges<N>(a.nh, cv, i);
+                const Probe<N> pr = probe_issue<N>(a.nh, cv, i);
                 // vertex-induced: an edge outside G_f between the two sides
                 // leaves no child (of this parent; the piece stays for others)
                 const uint32_t ty =
@@ -2123,7 +2143,7 @@ __device__ __forceinline__ void join_tiles(const TileArgs& a) {
                     L | (uint64_t)lu << (6 * M) | (uint64_t)lw << (6 * (M + 1)) | gid << 48;
                 lr[M] = lru;
                 lr[M + 1] = lrw;
-                got = children_tile<N, EXTRA>(a, f3, dtab, srb, cv, lr, i, ty, ec, PA, Lc, pslot,
+                got = children_tile<N, EXTRA>(a, f3, dtab, srb, cv, lr, i, ty, pr, PA, Lc, pslot,
                                               lu, lw, c);
                 emit += (unsigned long long)got;
                 bytes += 8ull * 2 * (M - 1) + 4ull * N * (unsigned long long)got;
