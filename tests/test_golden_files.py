@@ -1,7 +1,7 @@
-"""The stored oracle digests of the 256-graph batch workload
-(tests/golden/batch256_oracle_digests.json) describe the seeded graphs that
-``synth`` generates today, and the oracle reproduces them (its three
-quickest graphs are recomputed here)."""
+"""Consistency of the stored oracle results that are kept as digests: they
+describe the seeded graphs ``synth`` generates today, the oracle reproduces
+them where that takes seconds, and two independent oracle runs on the same
+graph agree where they overlap."""
 import hashlib
 import json
 import os
@@ -36,3 +36,19 @@ def test_batch_digests_match_the_generated_graphs_and_the_oracle():
                            gold["max_size"])
         assert len(pats) == e["patterns"]
         assert digest(pats) == e["digest"]
+
+
+def test_tenth_scale_size6_golden_agrees_with_size5_golden():
+    """The 1/10-scale 1M-vertex workload mined by the oracle to size 5 and,
+    in a separate run, to size 6: same graph, same per-size counts for sizes
+    2..5, and every sampled size-6 pattern has a support of at least t."""
+    g5 = json.load(open(os.path.join(HERE, "golden", "cl1m_tenth_t2000_s5.json")))
+    g6 = json.load(open(os.path.join(HERE, "golden", "cl1m_tenth_t2000_s6.json")))
+    assert g5["graph_sha256"] == g6["graph_sha256"] and g5["support"] == g6["support"]
+    counts = {}
+    for p in g5["patterns"]:
+        counts[str(p[0])] = counts.get(str(p[0]), 0) + 1
+    assert {k: v for k, v in g6["by_size"].items() if int(k) <= 5} == counts
+    assert sum(g6["by_size"].values()) == g6["patterns_total"]
+    assert len(g6["sample"]) == 1000
+    assert all(p[0] == 6 and p[3] >= g6["support"] for p in g6["sample"])

@@ -7,6 +7,7 @@ written by the oracle alone from patterns of its own 1/10-scale result): a
 pattern with a support must be reported with exactly that support, one
 below t must be absent.  The 1/10-scale graph of the same generator is
 checked to size 6 against the oracle's whole result."""
+import hashlib
 import itertools
 import json
 import os
@@ -193,6 +194,34 @@ def tenth_scale_golden(stem):
     assert gold["graph_sha256"] == synth.graph_sha256(w["src"], w["dst"], w["vertex_labels"])
     want = [(p[0], tuple(p[1]), p[2], p[3]) for p in gold["patterns"]]
     return w, gold, want
+
+
+def result_digest(patterns):
+    # the serialisation of tests/golden/make_golden.py's compact cases
+    h = hashlib.sha256()
+    for size, labels, adj, sup in patterns:
+        h.update(f"{size} {','.join(str(x) for x in labels)} {adj} {sup}\n".encode())
+    return h.hexdigest()
+
+
+def test_tenth_scale_size6_matches_whole_oracle_result():
+    """The same 1/10-scale graph mined to the configuration's stated size 6:
+    the whole result (142,684 patterns) equals the oracle's, by per-size
+    counts, a seeded sample of size-6 supports and the digest of the list."""
+    gold = json.load(open(os.path.join(HERE, "golden", "cl1m_tenth_t2000_s6.json")))
+    w = synth.workload(gold["workload"], **gold["overrides"])
+    assert gold["graph_sha256"] == synth.graph_sha256(w["src"], w["dst"], w["vertex_labels"])
+    with fsm.Graph(w["n"], w["src"], w["dst"], w["vertex_labels"]) as g:
+        say("cl1m at 1/10 scale: sizes 2..6")
+        r = fsm.mine(g, gold["support"], gold["max_size"])
+    by_size = {}
+    for p in r.patterns:
+        by_size[str(p[0])] = by_size.get(str(p[0]), 0) + 1
+    say(f"cl1m at 1/10 scale: {len(r)} patterns, by size {by_size}")
+    assert by_size == gold["by_size"]
+    present, absent = check_against_sampled(r, gold["sample"])
+    assert present == len(gold["sample"]) and absent == 0
+    assert result_digest(r.patterns) == gold["digest"]
 
 
 def test_tenth_scale_size5_matches_whole_oracle_result():
