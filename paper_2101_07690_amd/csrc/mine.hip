@@ -1593,24 +1593,25 @@ struct GroupBuild {
     uint32_t* wslot;    // group-table slot of each work item (tables up to 2^32 slots)
     unsigned* count;    // occupied slots
     uint32_t* flags;
-    unsigned long long* kpar;   // work items per joining vertex
 };
 
 __device__ __forceinline__ uint64_t group_key(int32_t k, int32_t pq, int i) {
     return (uint64_t)(uint32_t)k << 32 | (uint64_t)(uint32_t)pq << 3 | (uint64_t)i;
 }
 
+// One thread per parent row: its M work items (p, i), i = 0..M-1.
 __global__ void k_group_insert(GroupBuild b) {
-    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < b.nwork;
-         w += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = w / b.M;
-        const int i = (int)(w - p * b.M);
+    const int64_t rows = b.nwork / b.M;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < rows;
+         p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t* row = b.par + p * (b.M + 1);
-        const uint64_t key = group_key(row[i], row[b.M], i);
-        int64_t s = ht_probe(b.kv, b.mask, key, true, b.count, b.flags, OVF_QP);
-        b.wslot[w] = (uint32_t)s;   // an overflowed attempt's slots are never read
-        if (s >= 0) atomicAdd((unsigned long long*)&b.kv[2 * s + 1], 1ull);
-        atomicAdd(&b.kpar[row[i]], 1ull);
+        const int32_t pq = row[b.M];
+        for (int i = 0; i < b.M; ++i) {
+            const uint64_t key = group_key(row[i], pq, i);
+            const int64_t s = ht_probe(b.kv, b.mask, key, true, b.count, b.flags, OVF_QP);
+            b.wslot[p * b.M + i] = (uint32_t)s;   // an overflowed attempt's slots are never read
+            if (s >= 0) atomicAdd((unsigned long long*)&b.kv[2 * s + 1], 1ull);
+        }
     }
 }
 
@@ -1629,6 +1630,16 @@ __global__ void k_group_place(const uint64_t* kv, uint64_t slots, const int64_t*
         const uint64_t key = kv[2 * s];
         if (key == EMPTY_KEY) continue;
         goff[gid[s]] = atomicAdd(&kcursor[(int32_t)(key >> 32)], kv[2 * s + 1]);
+    }
+}
+
+// work items per joining vertex: the counts of its sub-groups (one atomic
+// per occupied slot rather than one per work item)
+__global__ void k_key_counts(const uint64_t* kv, uint64_t slots, unsigned long long* kpar) {
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < slots;
+         s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = kv[2 * s];
+        if (key != EMPTY_KEY) atomicAdd(&kpar[(uint32_t)(key >> 32)], (unsigned long long)kv[2 * s + 1]);
     }
 }
 
@@ -1658,13 +1669,16 @@ __global__ void k_key_tiles(const int32_t* gk, const int64_t* gcnt, const int64_
         tiles[g] = ((gcnt[g] + tile_p - 1) / tile_p) * ((npieces[gk[g]] + 63) / 64);
 }
 
+// One thread per parent row, as in k_group_insert.
 __global__ void k_group_fill(int64_t nwork, int M, const uint32_t* wslot, const int64_t* gid,
                              unsigned long long* cursor, int32_t* glist) {
-    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nwork;
-         w += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = gid[wslot[w]];
-        glist[atomicAdd(&cursor[g], 1ull)] = (int32_t)(w / M);
-    }
+    const int64_t rows = nwork / M;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < rows;
+         p += (int64_t)gridDim.x * blockDim.x)
+        for (int i = 0; i < M; ++i) {
+            const int64_t g = gid[wslot[p * M + i]];
+            glist[atomicAdd(&cursor[g], 1ull)] = (int32_t)p;
+        }
 }
 
 
@@ -3989,9 +4003,8 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
         FSM_LAUNCH_CHECK();
         cnt.zero();
         flags.zero();
-        kpar.zero();
-        GroupBuild b{P.emb.p, M, nwork, kv.p, cap - 1, wslot.p, cnt.p, flags.p, kpar.p};
-        k_group_insert<<<grid_for(nwork, TPB), TPB, 0, st>>>(b);
+        GroupBuild b{P.emb.p, M, nwork, kv.p, cap - 1, wslot.p, cnt.p, flags.p};
+        k_group_insert<<<grid_for(nwork / M, TPB), TPB, 0, st>>>(b);
         FSM_LAUNCH_CHECK();
         if (!(scalar_to_host(flags.p) & OVF_QP)) break;
         // slots are stored as 32-bit words
@@ -4002,6 +4015,9 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
     }
     // parent range of every key, then each sub-group's run inside it
     DBuf<int64_t> kpoff((size_t)n);
+    kpar.zero();
+    k_key_counts<<<grid_for((int64_t)cap, TPB), TPB, 0, st>>>(kv.p, cap, kpar.p);
+    FSM_LAUNCH_CHECK();
     scan_exclusive(reinterpret_cast<int64_t*>(kpar.p), kpoff.p, n);
     DBuf<unsigned long long> kcursor((size_t)n);
     FSM_HIP(hipMemcpyAsync(kcursor.p, kpoff.p, sizeof(int64_t) * (size_t)n,
@@ -4015,7 +4031,7 @@ void Miner::build_groups(const Level& P, int M, int64_t nwork, Groups& G,
                                                               soff.p);
     FSM_LAUNCH_CHECK();
     G.glist.alloc((size_t)nwork);
-    k_group_fill<<<grid_for(nwork, TPB), TPB, 0, st>>>(nwork, M, wslot.p, gid.p, soff.p,
+    k_group_fill<<<grid_for(nwork / M, TPB), TPB, 0, st>>>(nwork, M, wslot.p, gid.p, soff.p,
                                                        G.glist.p);
     FSM_LAUNCH_CHECK();
     // key groups = vertices with work, with their tile counts
