@@ -2586,12 +2586,13 @@ __global__ void k_mni(MniArgs a, const int64_t* ocnt) { mni(a, ocnt); }
 //
 // A batched call runs the last join level of each chunk as one replay of a
 // HIP graph: reset of the level's tables, domain pass, canonical forms,
-// merge into (pattern, orbit) bitmaps, orbit popcounts and MNI.  Every
-// kernel of the graph reads its arguments from a device descriptor, so one
-// instantiated graph serves every chunk whose level has the same shape
-// (size, table capacities, bitmap words); the host writes the chunk's
-// descriptor, replays, and synchronises once to read the overflow flags and
-// the patterns.  Nothing is cleared by memset nodes: k_level_reset fills.
+// merge into (pattern, orbit) bitmaps, orbit popcounts and MNI.  The reset
+// and the domain pass read their arguments from a device descriptor; the
+// other kernels' arguments are set in the executable graph before each
+// replay.  One instantiated graph serves every chunk of the same level size
+// and grid; the host writes the chunk's descriptor, replays, and
+// synchronises once to read the overflow flags and the patterns.  Nothing is
+// cleared by memset nodes: k_level_reset fills.
 struct LevelDesc {
     TileArgs t;
     CanonArgs ca;
@@ -3842,7 +3843,8 @@ void Miner::build_gf() {
     for (fsm_result* r : res) r->stats.filtered_edges = fnnz / 2;
 }
 
-// Per-vertex linear-probing neighbour tables of the CSR (row, col).
+// Per-vertex two-choice cuckoo neighbour tables of the CSR (row, col):
+// buckets of two slots, grown for the vertices whose insertion failed.
 void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
                              DBuf<int2>& tab) {
     const int64_t n = g->n;
