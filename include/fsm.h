@@ -264,8 +264,11 @@ int64_t fsm_graph_edges(const fsm_graph *g);
  *   out        receives the result handle
  * Errors: FSM_EINVAL (NULL graph/out, support < 1, max_size outside 2..7,
  * unknown mode bits, FSM_SAMPLED here); FSM_EUNSUPPORTED when more than
- * FSM_MAX_FREQ_LABELS labels occur on at least `support` vertices;
- * FSM_EOVERFLOW when a table cannot grow within device memory;
+ * FSM_MAX_FREQ_LABELS labels occur on at least `support` vertices, a
+ * frequent label has more than 2^26 vertices, a vertex would need more than
+ * 2^29 neighbour-table buckets, or a join has 2^31 or more parent
+ * embeddings; FSM_EOVERFLOW when a table cannot grow within device memory
+ * or a join's work-item grouping table would pass 2^32 slots;
  * FSM_ENOMEM / FSM_EDEVICE from the device. */
 int fsm_mine(const fsm_graph *g, int64_t support, int32_t max_size,
              uint32_t mode, fsm_result **out);
