@@ -1857,12 +1857,6 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
             if ((PA >> (8 * p + q)) & 1u) rpar |= rb[rk[p] << 3 | rk[q]];
     const uint32_t eku = rb[rki << 3 | rk[M]], ekw = rb[rki << 3 | rk[M + 1]];
     const uint32_t euw = rb[rk[M] << 3 | rk[M + 1]];
-    uint32_t cm[2 * M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        cm[2 * j] = rb[rk[j] << 3 | rk[M]];
-        cm[2 * j + 1] = rb[rk[j] << 3 | rk[M + 1]];
-    }
     const uint32_t want =
         ((1u << rki) | (1u << rk[M]) | (1u << rk[M + 1])) | ((uint32_t)rki << 8);
     // the adjacency reads were issued before the work above
@@ -1899,10 +1893,15 @@ __device__ __forceinline__ int children_tile(const TileArgs& a, const uint8_t* f
                                (uint64_t)lu << 24 | (uint64_t)lw << 18;
         uint32_t sub = allowed;
         for (;;) {
+            // pair bits of the subset's connecting edges (bit 2j: position
+            // j ~ u, 2j + 1: j ~ w); looked up only where a lane has a
+            // non-empty subset, which most waves do not
             uint32_t radj = r0;
+            if (sub) {
 #pragma unroll
-            for (int b = 0; b < 2 * M; ++b)
-                if ((sub >> b) & 1u) radj |= cm[b];
+                for (int b = 0; b < 2 * M; ++b)
+                    if ((sub >> b) & 1u) radj |= rb[rk[b >> 1] << 3 | rk[M + (b & 1)]];
+            }
             if (dtab[radj] == want) {
                 const uint64_t key = kbase | sub;
                 int64_t s;
