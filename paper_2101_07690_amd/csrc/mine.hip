@@ -274,14 +274,15 @@ __device__ __forceinline__ int64_t frequent_slot(const Rec& R, uint64_t key) {
 }
 
 // Adjacency test through per-vertex neighbour tables: vertex b owns a
-// two-choice cuckoo table of its G_f neighbours, nb(b) = pow2 >= deg(b)
-// buckets of two slots (load <= 1/2) at tab[off[b] .. off[b+1]), empty
-// slots -1.  A neighbour x sits in bucket h1(x) or h2(x), so a test reads
-// two 8-byte buckets -- no probe loop, the same work on every lane -- and a
-// wave testing one vertex b for many x stays within b's table.
+// two-choice cuckoo table of its G_f neighbours, nb(b) = pow2 >= 2 deg(b)
+// one-slot buckets (load <= 1/2) at tab[off[b] .. off[b+1]), empty slots
+// -1.  A neighbour x sits in bucket h1(x) or h2(x), so a test reads two
+// 4-byte words and makes two compares -- no probe loop, the same work on
+// every lane -- and a wave testing one vertex b for many x stays within
+// b's table.
 struct NbrHash {
     const uint32_t* off;   // n + 1, in buckets
-    const int2* tab;
+    const int32_t* tab;
 };
 
 __host__ __device__ __forceinline__ uint32_t nbr_hash(int32_t x) {
@@ -295,14 +296,9 @@ __host__ __device__ __forceinline__ uint32_t nbr_hash2(int32_t x) {
 }
 
 // b's table holds x (nb = its bucket count, o its first bucket)
-__device__ __forceinline__ bool nbr_has(const int2* tab, uint32_t o, uint32_t nb, int32_t x) {
-    // a bucket read as one 64-bit word (slot 0 low, slot 1 high)
-    const FSM_GLOBAL uint64_t* t = gmem(reinterpret_cast<const uint64_t*>(tab)) + o;
-    const uint64_t p = t[nbr_hash(x) & (nb - 1)];
-    const uint64_t q = t[nbr_hash2(x) & (nb - 1)];
-    const uint32_t y = (uint32_t)x;
-    return (uint32_t)p == y || (uint32_t)(p >> 32) == y || (uint32_t)q == y ||
-           (uint32_t)(q >> 32) == y;
+__device__ __forceinline__ bool nbr_has(const int32_t* tab, uint32_t o, uint32_t nb, int32_t x) {
+    const FSM_GLOBAL int32_t* t = gmem(tab) + o;
+    return t[nbr_hash(x) & (nb - 1)] == x || t[nbr_hash2(x) & (nb - 1)] == x;
 }
 
 __device__ __forceinline__ bool has_edge(const NbrHash& H, int32_t b, int32_t x) {
@@ -402,9 +398,9 @@ __global__ void k_gf_fill(const int32_t* row, const int32_t* col, const int32_t*
     }
 }
 
-// neighbour-table sizes: pow2 >= 2*deg, 0 for isolated vertices
 // Buckets of each vertex's neighbour table: the smallest power of two >=
-// deg (two slots each), times 2^grow[v] after failed builds.
+// 2 deg (one slot each), times 2^grow[v] after failed builds; 0 for an
+// isolated vertex.
 __global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, int64_t* nb,
                             unsigned* big) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
@@ -413,7 +409,7 @@ __global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, 
         int64_t c = 0;
         if (d > 0) {
             c = 1;
-            while (c < d) c <<= 1;
+            while (c < 2 * d) c <<= 1;
             c <<= grow[v];
         }
         if (c > NB_MAX) atomicOr(big, 1u);
@@ -427,7 +423,7 @@ __global__ void k_nbr_sizes(const int32_t* row, int64_t n, const uint8_t* grow, 
 constexpr int CUCKOO_STEPS = 512;
 
 __global__ void k_nbr_fill(const int32_t* row, const int32_t* col, int64_t n, const int64_t* off,
-                           int64_t total, uint32_t* off32, int2* tab, uint8_t* failed,
+                           int64_t total, uint32_t* off32, int32_t* tab, uint8_t* failed,
                            unsigned* nfailed) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
          v += (int64_t)gridDim.x * blockDim.x) {
@@ -435,28 +431,25 @@ __global__ void k_nbr_fill(const int32_t* row, const int32_t* col, int64_t n, co
         const int64_t o = off[v];
         off32[v] = (uint32_t)o;
         const uint32_t nb = (uint32_t)((v + 1 < n ? off[v + 1] : total) - o);
-        int2* t = tab + o;
-        for (uint32_t b = 0; b < nb; ++b) t[b] = make_int2(-1, -1);
+        int32_t* t = tab + o;
+        for (uint32_t b = 0; b < nb; ++b) t[b] = -1;
         bool ok = true;
         for (int32_t e = row[v]; e < row[v + 1] && ok; ++e) {
             int32_t x = col[e];
-            uint32_t b = nbr_hash(x) & (nb - 1);
-            int step = 0;
-            for (;; ++step) {
-                if (t[b].x < 0) { t[b].x = x; break; }
-                if (t[b].y < 0) { t[b].y = x; break; }
-                const uint32_t b2 = (nbr_hash(x) & (nb - 1)) == b ? (nbr_hash2(x) & (nb - 1))
-                                                                 : (nbr_hash(x) & (nb - 1));
-                if (b2 != b) {
-                    if (t[b2].x < 0) { t[b2].x = x; break; }
-                    if (t[b2].y < 0) { t[b2].y = x; break; }
-                }
+            uint32_t b = nbr_hash(x) & (nb - 1);   // the bucket x is tried in first
+            for (int step = 0;; ++step) {
+                if (t[b] < 0) { t[b] = x; break; }
+                const uint32_t h1 = nbr_hash(x) & (nb - 1), h2 = nbr_hash2(x) & (nb - 1);
+                const uint32_t alt = h1 == b ? h2 : h1;
+                if (t[alt] < 0) { t[alt] = x; break; }
                 if (step >= CUCKOO_STEPS) { ok = false; break; }
-                // displace a key of bucket b2 (alternating slots) and carry it on
-                int32_t y;
-                if (step & 1) { y = t[b2].y; t[b2].y = x; } else { y = t[b2].x; t[b2].x = x; }
+                // x takes the slot of bucket alt; the key it displaces moves
+                // on to its own other bucket
+                const int32_t y = t[alt];
+                t[alt] = x;
                 x = y;
-                b = b2;
+                const uint32_t y1 = nbr_hash(x) & (nb - 1), y2 = nbr_hash2(x) & (nb - 1);
+                b = y1 == alt ? y2 : y1;
             }
         }
         if (!ok) {
@@ -1746,12 +1739,12 @@ struct LaneCache {
 // test is two bucket reads.  Only the M - 1 positions other than i are
 // probed (position j of the jj-th probe is jj, or jj + 1 past i;
 // wave-uniform).  A bucket's byte offset is the lane's pre-shifted hash
-// masked by the table's (bucket count - 1) << 3.  The reads are issued
+// masked by the table's (bucket count - 1) << 2.  The reads are issued
 // first (probe_issue) and compared later (probe_bits), so that work not
 // depending on them can cover their latency.
 template <int N>
 struct Probe {
-    uint64_t bu1[N - 3], bu2[N - 3], bw1[N - 3], bw2[N - 3];
+    int32_t bu1[N - 3], bu2[N - 3], bw1[N - 3], bw2[N - 3];
     bool live[N - 3];
 };
 
@@ -1759,9 +1752,9 @@ template <int N>
 __device__ __forceinline__ Probe<N> probe_issue(const NbrHash& H, const int32_t (&cv)[N], int i) {
     constexpr int M = N - 2;
     const int32_t u = cv[M], w = cv[M + 1];
-    const uint32_t su1 = nbr_hash(u) << 3, su2 = nbr_hash2(u) << 3;
-    const uint32_t sw1 = nbr_hash(w) << 3, sw2 = nbr_hash2(w) << 3;
-    const FSM_GLOBAL uint64_t* tab = gmem(reinterpret_cast<const uint64_t*>(H.tab));
+    const uint32_t su1 = nbr_hash(u) << 2, su2 = nbr_hash2(u) << 2;
+    const uint32_t sw1 = nbr_hash(w) << 2, sw2 = nbr_hash2(w) << 2;
+    const FSM_GLOBAL int32_t* tab = gmem(H.tab);
     const FSM_CONST uint32_t* off = cmem(H.off);
     Probe<N> P;
 #pragma unroll
@@ -1773,10 +1766,10 @@ __device__ __forceinline__ Probe<N> probe_issue(const NbrHash& H, const int32_t 
         // the whole array (it exists) and its result is dropped.
         const uint32_t o = off[b], nb = off[b + 1] - o;
         P.live[jj] = nb != 0;
-        const uint32_t m8 = nb ? (nb - 1) << 3 : 0u;
+        const uint32_t m4 = nb ? (nb - 1) << 2 : 0u;
         const FSM_GLOBAL char* base = reinterpret_cast<const FSM_GLOBAL char*>(tab + (nb ? o : 0u));
         auto bucket = [&](uint32_t sh) {
-            return *reinterpret_cast<const FSM_GLOBAL uint64_t*>(base + (sh & m8));
+            return *reinterpret_cast<const FSM_GLOBAL int32_t*>(base + (sh & m4));
         };
         P.bu1[jj] = bucket(su1);
         P.bu2[jj] = bucket(su2);
@@ -1791,14 +1784,13 @@ __device__ __forceinline__ Probe<N> probe_issue(const NbrHash& H, const int32_t 
 template <int N>
 __device__ __forceinline__ uint32_t probe_bits(const Probe<N>& P, const int32_t (&cv)[N], int i) {
     constexpr int M = N - 2;
-    const uint32_t uu = (uint32_t)cv[M], ww = (uint32_t)cv[M + 1];
-    auto has = [](uint64_t x, uint32_t y) { return (uint32_t)x == y || (uint32_t)(x >> 32) == y; };
+    const int32_t uu = cv[M], ww = cv[M + 1];
     bool mu[M - 1], mw[M - 1];
     bool any = false;
 #pragma unroll
     for (int jj = 0; jj < M - 1; ++jj) {
-        mu[jj] = P.live[jj] && (has(P.bu1[jj], uu) || has(P.bu2[jj], uu));
-        mw[jj] = P.live[jj] && (has(P.bw1[jj], ww) || has(P.bw2[jj], ww));
+        mu[jj] = P.live[jj] && (P.bu1[jj] == uu || P.bu2[jj] == uu);
+        mw[jj] = P.live[jj] && (P.bw1[jj] == ww || P.bw2[jj] == ww);
         any = any || mu[jj] || mw[jj];
     }
     if (__ballot(any) == 0ull) return 0u;
@@ -3235,11 +3227,11 @@ struct Miner {
     DBuf<int32_t> frow, fcol;             // G_f
     int64_t fnnz = 0;
     DBuf<uint32_t> nhoff;
-    DBuf<int2> nhtab;
+    DBuf<int32_t> nhtab;
     NbrHash nh() const { return NbrHash{nhoff.p, nhtab.p}; }
     // vertex-induced mode: tables of the edges outside G_f (empty: none)
     DBuf<uint32_t> xhoff;
-    DBuf<int2> xhtab;
+    DBuf<int32_t> xhtab;
     NbrHash xh() const { return NbrHash{xhoff.p, xhtab.p}; }
     DBuf<uint64_t> mthr;            // matching sampling thresholds
     Sampling sampling() const {
@@ -3253,7 +3245,7 @@ struct Miner {
     void st_pieces(int n, const Sampling& smp, DBuf<int64_t>& cnt, DBuf<int64_t>& off,
                    DBuf<uint64_t>& key, DBuf<uint8_t>& code);
     void neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
-                          DBuf<int2>& tab);
+                          DBuf<int32_t>& tab);
     DBuf<int64_t> npieces;
     DBuf<int32_t> leafoff;
     DBuf<uint8_t> f3;
@@ -3845,7 +3837,7 @@ void Miner::build_gf() {
 // Per-vertex two-choice cuckoo neighbour tables of the CSR (row, col):
 // buckets of two slots, grown for the vertices whose insertion failed.
 void Miner::neighbour_tables(const int32_t* row, const int32_t* col, DBuf<uint32_t>& off,
-                             DBuf<int2>& tab) {
+                             DBuf<int32_t>& tab) {
     const int64_t n = g->n;
     DBuf<int64_t> nb((size_t)n + 1);
     DBuf<uint8_t> grow((size_t)n), failed((size_t)n);
