@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 _lib = None
-MAXN = 7
+MAXN = 8
 
 
 def _load():

@@ -48,7 +48,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OMAX 7                     /* largest pattern size handled */
+#define OMAX 8                     /* largest pattern size handled */
 #define OPAIRS (OMAX * (OMAX - 1) / 2)
 
 /* ------------------------------------------------------------------ graph */

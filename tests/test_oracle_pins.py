@@ -195,7 +195,7 @@ def test_rejects_bad_input():
     with pytest.raises(ValueError):
         oracle.mine(2, s, t, np.array([0, 0], np.int32), 0, 3)
     with pytest.raises(ValueError):
-        oracle.mine(2, s, t, np.array([0, 0], np.int32), 1, 8)
+        oracle.mine(2, s, t, np.array([0, 0], np.int32), 1, oracle.MAXN + 1)
     with pytest.raises(ValueError):
         oracle.mine(2, np.array([0], np.int32), np.array([5], np.int32),
                     np.array([0, 0], np.int32), 1, 3)
