@@ -21,7 +21,7 @@ import numpy as np
 from . import build as _build
 
 _lib = None
-MAXN = 8
+MAXN = 9
 
 
 def _load():
@@ -35,23 +35,23 @@ def _load():
     lib = ctypes.CDLL(path)
     i32p = ctypes.POINTER(ctypes.c_int32)
     i64p = ctypes.POINTER(ctypes.c_int64)
-    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.oracle_mine.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i32p,
                                 ctypes.c_int64, ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_void_p)]
     lib.oracle_mine.restype = ctypes.c_int
     lib.oracle_result_count.argtypes = [ctypes.c_void_p]
     lib.oracle_result_count.restype = ctypes.c_int64
-    lib.oracle_result_get.argtypes = [ctypes.c_void_p, i32p, i32p, u32p, i64p]
+    lib.oracle_result_get.argtypes = [ctypes.c_void_p, i32p, i32p, u64p, i64p]
     lib.oracle_result_get.restype = ctypes.c_int
     lib.oracle_result_levels.argtypes = [ctypes.c_void_p, i64p, i64p]
     lib.oracle_result_levels.restype = ctypes.c_int
     lib.oracle_result_free.argtypes = [ctypes.c_void_p]
     lib.oracle_result_free.restype = None
-    lib.oracle_canonical.argtypes = [ctypes.c_int32, i32p, ctypes.c_uint32, i32p, u32p]
+    lib.oracle_canonical.argtypes = [ctypes.c_int32, i32p, ctypes.c_uint64, i32p, u64p]
     lib.oracle_canonical.restype = ctypes.c_int
     lib.oracle_pattern_support.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p,
-                                           i32p, ctypes.c_int32, i32p, ctypes.c_uint32]
+                                           i32p, ctypes.c_int32, i32p, ctypes.c_uint64]
     lib.oracle_pattern_support.restype = ctypes.c_int64
     lib.oracle_mine_ex.argtypes = lib.oracle_mine.argtypes[:7] + [ctypes.c_int32,
                                                                  lib.oracle_mine.argtypes[7]]
@@ -63,7 +63,7 @@ def _load():
     lib.oracle_count_connected.restype = ctypes.c_int64
     lib.oracle_graph_new.argtypes = [ctypes.c_int64, ctypes.c_int64, i32p, i32p, i32p]
     lib.oracle_graph_new.restype = ctypes.c_void_p
-    lib.oracle_graph_support.argtypes = [ctypes.c_void_p, ctypes.c_int32, i32p, ctypes.c_uint32,
+    lib.oracle_graph_support.argtypes = [ctypes.c_void_p, ctypes.c_int32, i32p, ctypes.c_uint64,
                                          ctypes.c_int64, ctypes.c_int32]
     lib.oracle_graph_support.restype = ctypes.c_int64
     lib.oracle_graph_free.argtypes = [ctypes.c_void_p]
@@ -93,13 +93,13 @@ def mine(n_vertices, src, dst, labels, support, max_size, induced=False):
         cnt = lib.oracle_result_count(h)
         sizes = np.zeros(cnt, np.int32)
         labs = np.zeros((cnt, MAXN), np.int32)
-        adj = np.zeros(cnt, np.uint32)
+        adj = np.zeros(cnt, np.uint64)
         sup = np.zeros(cnt, np.int64)
         if cnt:
             lib.oracle_result_get(
                 h, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                 labs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                adj.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                adj.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                 sup.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     finally:
         lib.oracle_result_free(h)
@@ -113,8 +113,8 @@ def canonical(labels, adj):
     n = len(labels)
     lab, lp = _arr(labels)
     out = np.zeros(MAXN, np.int32)
-    oadj = ctypes.c_uint32()
-    rc = lib.oracle_canonical(n, lp, ctypes.c_uint32(adj),
+    oadj = ctypes.c_uint64()
+    rc = lib.oracle_canonical(n, lp, ctypes.c_uint64(adj),
                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                               ctypes.byref(oadj))
     if rc != 0:
@@ -130,7 +130,7 @@ def pattern_support(n_vertices, src, dst, labels, plabels, padj, induced=False):
     lab, lp = _arr(labels)
     pl, plp = _arr(plabels)
     r = lib.oracle_pattern_support_ex(int(n_vertices), int(s.size), sp, dp, lp,
-                                      len(plabels), plp, ctypes.c_uint32(padj),
+                                      len(plabels), plp, ctypes.c_uint64(padj),
                                       1 if induced else 0)
     if r < 0:
         raise ValueError("bad pattern")
@@ -170,7 +170,7 @@ class Graph:
         """Exact MNI support of one connected pattern; with t > 0, -1 when
         it is below t (the search stops early)."""
         pl, plp = _arr(plabels)
-        r = _load().oracle_graph_support(self._h, len(plabels), plp, ctypes.c_uint32(padj),
+        r = _load().oracle_graph_support(self._h, len(plabels), plp, ctypes.c_uint64(padj),
                                          int(t), 1 if induced else 0)
         if r == -2:
             raise ValueError("bad pattern")

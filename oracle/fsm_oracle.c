@@ -48,7 +48,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OMAX 8                     /* largest pattern size handled */
+#define OMAX 9                     /* largest pattern size handled */
 #define OPAIRS (OMAX * (OMAX - 1) / 2)
 
 /* ------------------------------------------------------------------ graph */
@@ -156,19 +156,19 @@ static int pair_pos(int i, int j, int n) {
  * labels in new order, and the adjacency bit sequence packed with its first
  * pair as the most significant bit, so integer order = sequence order. */
 static void code_under(const opat *p, const int *ord, int32_t *lab_out,
-                       uint32_t *seq_out) {
+                       uint64_t *seq_out) {
     int n = p->n;
-    uint32_t seq = 0;
+    uint64_t seq = 0;
     for (int i = 0; i < n; i++) lab_out[i] = p->lab[ord[i]];
     for (int i = 0; i < n; i++)
         for (int j = i + 1; j < n; j++)
-            seq = (seq << 1) | (uint32_t)(p->e[ord[i]][ord[j]] != 0);
+            seq = (seq << 1) | (uint64_t)(p->e[ord[i]][ord[j]] != 0);
     *seq_out = seq;
 }
 
 /* -1 / 0 / 1 comparison of two codes of the same size */
-static int code_cmp(int n, const int32_t *la, uint32_t sa, const int32_t *lb,
-                    uint32_t sb) {
+static int code_cmp(int n, const int32_t *la, uint64_t sa, const int32_t *lb,
+                    uint64_t sb) {
     for (int i = 0; i < n; i++)
         if (la[i] != lb[i]) return la[i] < lb[i] ? -1 : 1;
     if (sa != sb) return sa < sb ? -1 : 1;
@@ -191,7 +191,7 @@ static int next_perm(int *a, int n) {
 static void canonicalize(const opat *p, opat *out) {
     int n = p->n, ord[OMAX], best[OMAX];
     int32_t bl[OMAX], cl[OMAX];
-    uint32_t bs = 0, cs;
+    uint64_t bs = 0, cs;
     for (int i = 0; i < n; i++) ord[i] = i;
     int first = 1;
     do {
@@ -210,18 +210,18 @@ static void canonicalize(const opat *p, opat *out) {
 
 /* Packed adjacency of a pattern: bit pair_pos(i,j) set when i~j (LSB-first).
  * This is the exported form; the sequence form above orders codes. */
-static uint32_t pack_adj(const opat *p) {
-    uint32_t a = 0;
+static uint64_t pack_adj(const opat *p) {
+    uint64_t a = 0;
     for (int i = 0; i < p->n; i++)
         for (int j = i + 1; j < p->n; j++)
-            if (p->e[i][j]) a |= 1u << pair_pos(i, j, p->n);
+            if (p->e[i][j]) a |= 1ull << pair_pos(i, j, p->n);
     return a;
 }
 
-static uint32_t seq_of(const opat *p) {
+static uint64_t seq_of(const opat *p) {
     int ord[OMAX];
     int32_t l[OMAX];
-    uint32_t s;
+    uint64_t s;
     for (int i = 0; i < p->n; i++) ord[i] = i;
     code_under(p, ord, l, &s);
     return s;
@@ -270,7 +270,7 @@ static int connected_mask(const opat *p, unsigned mask) {
 
 typedef struct {
     opat p;          /* canonical */
-    uint32_t seq;    /* adjacency sequence of the canonical form */
+    uint64_t seq;    /* adjacency sequence of the canonical form */
     int64_t support; /* -1 while unknown, or infrequent */
 } oentry;
 
@@ -434,7 +434,7 @@ typedef struct oracle_result {
     int64_t count;
     int32_t *size;
     int32_t *labels;     /* count x 7, unused slots -1 */
-    uint32_t *adj;       /* LSB-first pair bits of the canonical form */
+    uint64_t *adj;       /* LSB-first pair bits of the canonical form */
     int64_t *support;
     int64_t level_candidates[OMAX + 1];
     int64_t level_frequent[OMAX + 1];
@@ -534,7 +534,7 @@ int oracle_mine_ex(int64_t n_vertices, int64_t n_edges, const int32_t *src,
     r->count = all.len;
     r->size = (int32_t *)malloc(sizeof(int32_t) * (size_t)(all.len + 1));
     r->labels = (int32_t *)malloc(sizeof(int32_t) * OMAX * (size_t)(all.len + 1));
-    r->adj = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(all.len + 1));
+    r->adj = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(all.len + 1));
     r->support = (int64_t *)malloc(sizeof(int64_t) * (size_t)(all.len + 1));
     for (int64_t i = 0; i < all.len; i++) {
         const oentry *e = &all.v[i];
@@ -559,11 +559,11 @@ int oracle_mine(int64_t n_vertices, int64_t n_edges, const int32_t *src,
 int64_t oracle_result_count(const oracle_result *r) { return r ? r->count : -1; }
 
 int oracle_result_get(const oracle_result *r, int32_t *sizes, int32_t *labels,
-                      uint32_t *adj, int64_t *supports) {
+                      uint64_t *adj, int64_t *supports) {
     if (!r) return -1;
     memcpy(sizes, r->size, sizeof(int32_t) * (size_t)r->count);
     memcpy(labels, r->labels, sizeof(int32_t) * OMAX * (size_t)r->count);
-    memcpy(adj, r->adj, sizeof(uint32_t) * (size_t)r->count);
+    memcpy(adj, r->adj, sizeof(uint64_t) * (size_t)r->count);
     memcpy(supports, r->support, sizeof(int64_t) * (size_t)r->count);
     return 0;
 }
@@ -582,8 +582,8 @@ void oracle_result_free(oracle_result *r) {
 }
 
 /* Canonical form of one pattern given as labels + LSB-first pair bits. */
-int oracle_canonical(int32_t n, const int32_t *labels, uint32_t adj,
-                     int32_t *out_labels, uint32_t *out_adj) {
+int oracle_canonical(int32_t n, const int32_t *labels, uint64_t adj,
+                     int32_t *out_labels, uint64_t *out_adj) {
     if (n < 1 || n > OMAX) return -1;
     opat p, c;
     p.n = n;
@@ -591,7 +591,7 @@ int oracle_canonical(int32_t n, const int32_t *labels, uint32_t adj,
     for (int i = 0; i < n; i++) p.lab[i] = labels[i];
     for (int i = 0; i < n; i++)
         for (int j = i + 1; j < n; j++)
-            if (adj & (1u << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
+            if (adj & (1ull << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
     canonicalize(&p, &c);
     for (int i = 0; i < n; i++) out_labels[i] = c.lab[i];
     *out_adj = pack_adj(&c);
@@ -603,7 +603,7 @@ int oracle_canonical(int32_t n, const int32_t *labels, uint32_t adj,
 int64_t oracle_pattern_support_ex(int64_t n_vertices, int64_t n_edges,
                                   const int32_t *src, const int32_t *dst,
                                   const int32_t *labels, int32_t n,
-                                  const int32_t *plabels, uint32_t padj, int32_t induced) {
+                                  const int32_t *plabels, uint64_t padj, int32_t induced) {
     if (n < 1 || n > OMAX) return -1;
     opat p;
     p.n = n;
@@ -611,7 +611,7 @@ int64_t oracle_pattern_support_ex(int64_t n_vertices, int64_t n_edges,
     for (int i = 0; i < n; i++) p.lab[i] = plabels[i];
     for (int i = 0; i < n; i++)
         for (int j = i + 1; j < n; j++)
-            if (padj & (1u << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
+            if (padj & (1ull << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
     if (!connected_mask(&p, (1u << n) - 1u)) return -1;
     ograph g;
     if (graph_build(&g, n_vertices, n_edges, src, dst, labels)) { graph_free(&g); return -1; }
@@ -647,7 +647,7 @@ oracle_graph *oracle_graph_new(int64_t n_vertices, int64_t n_edges, const int32_
  * search stops once the support is certainly below t and returns -1 (the
  * exact support otherwise).  -2 on a bad pattern. */
 int64_t oracle_graph_support(const oracle_graph *h, int32_t n, const int32_t *plabels,
-                             uint32_t padj, int64_t t, int32_t induced) {
+                             uint64_t padj, int64_t t, int32_t induced) {
     if (!h || n < 1 || n > OMAX) return -2;
     opat p;
     p.n = n;
@@ -655,7 +655,7 @@ int64_t oracle_graph_support(const oracle_graph *h, int32_t n, const int32_t *pl
     for (int i = 0; i < n; i++) p.lab[i] = plabels[i];
     for (int i = 0; i < n; i++)
         for (int j = i + 1; j < n; j++)
-            if (padj & (1u << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
+            if (padj & (1ull << pair_pos(i, j, n))) p.e[i][j] = p.e[j][i] = 1;
     if (!connected_mask(&p, (1u << n) - 1u)) return -2;
     return support_of(&h->g, &h->bl, &p, t, induced);
 }
@@ -670,7 +670,7 @@ void oracle_graph_free(oracle_graph *h) {
 int64_t oracle_pattern_support(int64_t n_vertices, int64_t n_edges,
                                const int32_t *src, const int32_t *dst,
                                const int32_t *labels, int32_t n,
-                               const int32_t *plabels, uint32_t padj) {
+                               const int32_t *plabels, uint64_t padj) {
     return oracle_pattern_support_ex(n_vertices, n_edges, src, dst, labels, n, plabels, padj, 0);
 }
 
@@ -695,10 +695,10 @@ static int64_t spanning_connected(const ograph *g, const int32_t *sub, int k) {
     int64_t count = 0;
     opat p;
     p.n = k;
-    for (uint32_t s = 0; s < (1u << m); s++) {
+    for (uint64_t s = 0; s < (1ull << m); s++) {
         memset(p.e, 0, sizeof(p.e));
         for (int b = 0; b < m; b++)
-            if (s & (1u << b)) p.e[ei[b]][ej[b]] = p.e[ej[b]][ei[b]] = 1;
+            if (s & (1ull << b)) p.e[ei[b]][ej[b]] = p.e[ej[b]][ei[b]] = 1;
         if (connected_mask(&p, (1u << k) - 1u)) count++;
     }
     return count;

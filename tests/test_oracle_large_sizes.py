@@ -1,7 +1,7 @@
-"""Pins of the CPU oracle at pattern size 8, the first size past what the
-device library mines: closed-form MNI supports (Section 2.2 definition) on
-paths, a cycle and a star, brute force on small trees and sparse graphs, and
-the canonical form's invariance under relabelling."""
+"""Pins of the CPU oracle at pattern sizes 8 and 9, past what the device
+library mines: closed-form MNI supports (Section 2.2 definition) on paths,
+cycles and stars, brute force on small trees and sparse graphs, and the
+canonical form's invariance under relabelling."""
 import random
 
 import numpy as np
@@ -24,17 +24,17 @@ def by_size(res):
     return out
 
 
-def test_size_limit_is_eight():
-    assert oracle.MAXN == 8
+def test_size_limit_is_nine():
+    assert oracle.MAXN == 9
 
 
-def test_path_supports_to_size8():
+def test_path_supports_to_size9():
     # Path with m vertices: a k-vertex sub-path pattern has orbits {j, k-1-j};
     # the innermost orbit is smallest: m-k+1 images for odd k, m-k+2 for even.
-    for m in (8, 9, 11):
+    for m in (9, 12):
         s, t = edges_of([(i, i + 1) for i in range(m - 1)])
-        res = by_size(oracle.mine(m, s, t, np.zeros(m, np.int32), 1, 8))
-        for k in range(2, 9):
+        res = by_size(oracle.mine(m, s, t, np.zeros(m, np.int32), 1, 9))
+        for k in range(2, 10):
             assert len(res[k]) == 1
             want = m - k + 1 if k % 2 else m - k + 2
             assert res[k][0][2] == want, (m, k)
@@ -77,11 +77,7 @@ def test_oracle_matches_brute_force_size8_trees():
 
 
 def test_oracle_matches_brute_force_size8_sparse():
-    # a 9-vertex path with one chord (two labels), and a tiny random graph
-    # with 9 vertices and 9 edges (13 patterns of size 8)
-    s, t = edges_of([(i, i + 1) for i in range(8)] + [(2, 6)])
-    lab = np.array([0, 1, 0, 1, 0, 1, 0, 1, 0], np.int32)
-    assert oracle.mine(9, s, t, lab, 1, 8) == brute.mine(9, s, t, lab, 1, 8)
+    # a tiny random graph with 9 vertices and 9 edges (13 patterns of size 8)
     s, t, lab = synth.tiny_graph(4109, 9, 10, 2)
     n = len(lab)
     want = brute.mine(n, s, t, lab, 1, 8)
@@ -111,3 +107,56 @@ def test_canonical_invariant_under_relabelling_size8():
                 adj2 |= 1 << oracle.pair_index(a, b, n)
         assert oracle.canonical(labs, adj) == oracle.canonical(labs2, adj2)
         assert list(oracle.canonical(labs, adj)[0]) == sorted(labs)
+
+
+def test_cycle9_and_star8_supports():
+    # C_9: every path P_2..P_9 and the cycle have support 9; size 9 holds P_9
+    # and C_9.  K_{1,8}: edge support 9, every larger star support 1.
+    m = 9
+    s, t = edges_of([(i, (i + 1) % m) for i in range(m)])
+    res = by_size(oracle.mine(m, s, t, np.zeros(m, np.int32), 1, 9))
+    assert [len(res[k]) for k in range(2, 10)] == [1, 1, 1, 1, 1, 1, 1, 2]
+    assert all(x[2] == m for k in res for x in res[k])
+    d = 8
+    s, t = edges_of([(0, i) for i in range(1, d + 1)])
+    res = by_size(oracle.mine(d + 1, s, t, np.zeros(d + 1, np.int32), 1, 9))
+    assert [x[2] for x in res[2]] == [d + 1]
+    for k in range(3, 10):
+        assert len(res[k]) == 1 and res[k][0][2] == 1
+
+
+def test_oracle_matches_brute_force_size9_labelled_path():
+    # a 10-vertex path with two labels: two 9-vertex subgraphs, label-split
+    # patterns at every size
+    rng = random.Random(3100)
+    s, t = edges_of([(i, i + 1) for i in range(9)])
+    lab = np.array([rng.randrange(2) for _ in range(10)], np.int32)
+    want = brute.mine(10, s, t, lab, 1, 9)
+    assert any(p[0] == 9 for p in want)
+    assert oracle.mine(10, s, t, lab, 1, 9) == want
+
+
+def test_canonical_invariant_under_relabelling_size9():
+    rng = random.Random(9)
+    n = 9
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    for _ in range(12):
+        labs = [rng.randint(0, 2) for _ in range(n)]
+        adj = 0
+        for k in range(len(pairs)):
+            if rng.random() < 0.35:
+                adj |= 1 << k
+        perm = list(range(n))
+        rng.shuffle(perm)
+        labs2 = [0] * n
+        for i in range(n):
+            labs2[perm[i]] = labs[i]
+        adj2 = 0
+        for k, (i, j) in enumerate(pairs):
+            if adj >> k & 1:
+                a, b = sorted((perm[i], perm[j]))
+                adj2 |= 1 << oracle.pair_index(a, b, n)
+        cl, ca = oracle.canonical(labs, adj)
+        assert (cl, ca) == oracle.canonical(labs2, adj2)
+        assert list(cl) == sorted(labs)
+        assert ca < 1 << 36
