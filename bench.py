@@ -378,7 +378,7 @@ def main():
                          "writes this many MiB (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 

@@ -98,7 +98,7 @@ typedef enum {
     FSM_ENOMEM = -2,       /* device or host allocation failed */
     FSM_EDEVICE = -3,      /* a HIP runtime call or kernel failed */
     FSM_EOVERFLOW = -4,    /* a size limit was exceeded (see message) */
-    FSM_EUNSUPPORTED = -5  /* valid request outside this build's limits */
+    FSM_EUNSUPPORTED = -5  /* valid request outside the library's size limits */
 } fsm_status;
 
 /* Per-level counters of one mining call (index = pattern size). */
