@@ -28,9 +28,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    path = _build.LIB
-    if not os.path.exists(path) or \
-            os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+    # FSM_ORACLE_LIB: another build of the same source (the sanitized one)
+    path = os.environ.get("FSM_ORACLE_LIB") or _build.LIB
+    if path == _build.LIB and (not os.path.exists(path) or
+                               os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
         _build.build()
     lib = ctypes.CDLL(path)
     i32p = ctypes.POINTER(ctypes.c_int32)

@@ -20,5 +20,16 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(out: str) -> str:
+    """The same source built with AddressSanitizer and UndefinedBehavior-
+    Sanitizer (host code only) into ``out``; a process that loads it must
+    preload the ASan runtime (tests/test_oracle_sanitized.py)."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                           "-std=c99", "-Wall", "-Wextra", "-Wno-unused-parameter",
+                           "-shared", "-fPIC", SRC, "-o", out])
+    return out
+
+
 if __name__ == "__main__":
     print(build())
